@@ -1,0 +1,322 @@
+"""Plain FP64 CPU oracle for the Trotterized adiabatic Z2 lattice-gauge evolution.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
+with the GPU library (``paper_1910_08020_amd``) and never imports it.
+
+The heavy loops live in ``lgt_oracle.c`` (plain C, FP64); this module wraps
+them with ctypes and adds the pieces that follow directly from the paper's
+formulas:
+
+* the stepwise schedule of Sec. 2.2 (``g_{k,m} = (k-1) g_s + m delta``: the
+  coupling of a substep is taken at its right end), in the paper's form
+  ``H = Z + g X`` and in the form ``H(s) = -h_x sum sigma^x - s h_p sum U_p``
+  where the plaquette coefficient ramps instead;
+* expectation values normalised as <psi|O|psi>/<psi|psi> (Sec. 2.4).
+
+Each function names the passage it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lgt_oracle.c")
+_LIB = os.path.join(_HERE, "liblgt_oracle.so")
+
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_dbl_p = ctypes.POINTER(ctypes.c_double)
+_c_u64_p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (FP64, no fast-math, OpenMP loops)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        L.orc_counts.argtypes = [ctypes.c_int, _c_int_p, _c_int_p, _c_int_p, _c_int_p]
+        L.orc_plaquettes.argtypes = [ctypes.c_int, _c_int_p, _c_int_p]
+        L.orc_stars.argtypes = [ctypes.c_int, _c_int_p, _c_int_p]
+        L.orc_walk_links.argtypes = [ctypes.c_int, _c_int_p, ctypes.c_int, _c_int_p,
+                                     ctypes.c_int, _c_int_p]
+        L.orc_init_plus.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_init_basis.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64]
+        L.orc_rx_link.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.orc_x_layer.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]
+        L.orc_plaq_layer.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int_p,
+                                     ctypes.c_double]
+        for name in ("orc_evolve", "orc_evolve_circuit"):
+            f = getattr(L, name)
+            f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int_p,
+                          ctypes.c_longlong, _c_dbl_p, _c_dbl_p, ctypes.c_double,
+                          ctypes.c_int]
+            f.restype = ctypes.c_int
+        L.orc_cnot.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_rz.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.orc_rx.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.orc_plaq_gadget.argtypes = [ctypes.c_void_p, ctypes.c_int, _c_int_p, ctypes.c_double]
+        L.orc_norm2.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_norm2.restype = ctypes.c_double
+        L.orc_expect_z.argtypes = [ctypes.c_void_p, ctypes.c_int, _c_int_p, ctypes.c_int]
+        L.orc_expect_z.restype = ctypes.c_double
+        L.orc_expect_x.argtypes = [ctypes.c_void_p, ctypes.c_int, _c_int_p, ctypes.c_int]
+        L.orc_expect_x.restype = ctypes.c_double
+        L.orc_zdos.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int_p, _c_dbl_p]
+        L.orc_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_uniform.restype = ctypes.c_double
+        L.orc_sample.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64,
+                                 ctypes.c_uint64, _c_u64_p]
+        L.orc_sample.restype = ctypes.c_int
+        L.orc_cdf.argtypes = [ctypes.c_void_p, ctypes.c_int, _c_dbl_p]
+        _lib = L
+    return _lib
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(_c_int_p)
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_c_dbl_p)
+
+
+def _state_arg(psi: np.ndarray, N: int):
+    if psi.dtype != np.complex128 or not psi.flags.c_contiguous or psi.size != (1 << N):
+        raise ValueError("state must be a contiguous complex128 array of 2^N amplitudes")
+    return psi.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# lattice (Sec. 2.1 and the caption of Fig. 1)
+# ---------------------------------------------------------------------------
+class Lattice:
+    """Periodic d-dimensional lattice, d in {2, 3}; links carry the qubits."""
+
+    def __init__(self, d: int, L):
+        L = list(L)
+        if len(L) != d:
+            raise ValueError("need one extent per dimension")
+        self.d = d
+        self.L = L
+        Lc = np.asarray(L, dtype=np.int32)
+        ns, nl, npq = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        if lib().orc_counts(d, _ip(Lc), ctypes.byref(ns), ctypes.byref(nl),
+                            ctypes.byref(npq)) != 0:
+            raise ValueError("unsupported lattice")
+        self.n_sites, self.n_links, self.n_plaq = ns.value, nl.value, npq.value
+        self.plaq = np.zeros((self.n_plaq, 4), dtype=np.int32)
+        lib().orc_plaquettes(d, _ip(Lc), _ip(self.plaq))
+        self.stars = np.zeros((self.n_sites, 2 * d), dtype=np.int32)
+        lib().orc_stars(d, _ip(Lc), _ip(self.stars))
+        self._Lc = Lc
+
+    @property
+    def N(self) -> int:
+        return self.n_links
+
+    def walk(self, start_site: int, moves) -> np.ndarray:
+        """Links of a closed walk; moves are +-(mu+1) (a Wegner-Wilson contour)."""
+        mv = np.asarray(moves, dtype=np.int32)
+        out = np.zeros(len(mv), dtype=np.int32)
+        k = lib().orc_walk_links(self.d, _ip(self._Lc), start_site, _ip(mv), len(mv), _ip(out))
+        if k < 0:
+            raise ValueError("bad walk")
+        return out[:k].copy()
+
+    def rect_loop(self, start_site: int, mu: int, nu: int, a: int, b: int) -> np.ndarray:
+        """Boundary of an a x b rectangle in the (mu, nu) plane, walked counter-clockwise."""
+        moves = [mu + 1] * a + [nu + 1] * b + [-(mu + 1)] * a + [-(nu + 1)] * b
+        return self.walk(start_site, moves)
+
+    def line(self, start_site: int, mu: int) -> np.ndarray:
+        """Non-contractible loop C_mu: L_mu links straight along mu (Sec. 2.1)."""
+        return self.walk(start_site, [mu + 1] * self.L[mu])
+
+    def site(self, x) -> int:
+        s, stride = 0, 1
+        for mu in range(self.d):
+            s += (x[mu] % self.L[mu]) * stride
+            stride *= self.L[mu]
+        return s
+
+
+# ---------------------------------------------------------------------------
+# schedule (Sec. 2.2)
+# ---------------------------------------------------------------------------
+def schedule_plaquette_ramp(T: float, n_steps: int, h_x: float, h_p: float,
+                            midpoint: bool = False):
+    """H_j = -h_x sum sigma^x - s_j h_p sum U_p, s_j = j/n (right end of step j).
+
+    The right-end rule mirrors g_{k,m} = (k-1) g_s + m delta of Sec. 2.2: the
+    first substep already uses delta and the last one uses the final value.
+    Returns (dt, cx[n], cz[n]).
+    """
+    j = np.arange(1, n_steps + 1, dtype=np.float64)
+    s = (j - 0.5) / n_steps if midpoint else j / n_steps
+    dt = T / n_steps
+    cx = np.full(n_steps, float(h_x))
+    cz = s * float(h_p)
+    return dt, cx, cz
+
+
+def schedule_coupling_ramp(T: float, n_steps: int, g0: float, g1: float,
+                           midpoint: bool = False):
+    """The paper's form H = Z + g X = -sum U_p - g sum sigma^x, g from g0 to g1.
+
+    Substep j (1-based) uses g_j = g0 + (g1 - g0) j / n, the same right-end
+    rule as g_{k,m} = (k-1) g_s + m delta with g_s = (g1-g0) n_sub / n.
+    """
+    j = np.arange(1, n_steps + 1, dtype=np.float64)
+    f = (j - 0.5) / n_steps if midpoint else j / n_steps
+    dt = T / n_steps
+    cx = g0 + (g1 - g0) * f
+    cz = np.ones(n_steps)
+    return dt, cx, cz
+
+
+# ---------------------------------------------------------------------------
+# states and evolution
+# ---------------------------------------------------------------------------
+def plus_state(N: int) -> np.ndarray:
+    psi = np.empty(1 << N, dtype=np.complex128)
+    lib().orc_init_plus(_state_arg(psi, N), N)
+    return psi
+
+
+def basis_state(N: int, b0: int) -> np.ndarray:
+    psi = np.empty(1 << N, dtype=np.complex128)
+    lib().orc_init_basis(_state_arg(psi, N), N, b0)
+    return psi
+
+
+def evolve(psi: np.ndarray, lat: Lattice, dt: float, cx, cz, order: int,
+           form: str = "fused") -> np.ndarray:
+    """In-place Trotterized evolution, eq. (a) (order 1) or eq. (s) (order 2)."""
+    N = lat.N
+    cx = np.ascontiguousarray(cx, dtype=np.float64)
+    cz = np.ascontiguousarray(cz, dtype=np.float64)
+    if cx.shape != cz.shape:
+        raise ValueError("cx and cz must have one entry per step")
+    f = lib().orc_evolve if form == "fused" else lib().orc_evolve_circuit
+    rc = f(_state_arg(psi, N), N, lat.n_plaq, _ip(lat.plaq), len(cx), _dp(cx), _dp(cz),
+           float(dt), int(order))
+    if rc != 0:
+        raise ValueError("bad order")
+    return psi
+
+
+def x_layer(psi, N, alpha):
+    lib().orc_x_layer(_state_arg(psi, N), N, float(alpha))
+    return psi
+
+
+def plaq_layer(psi, lat: Lattice, theta):
+    lib().orc_plaq_layer(_state_arg(psi, lat.N), lat.N, lat.n_plaq, _ip(lat.plaq), float(theta))
+    return psi
+
+
+def cnot(psi, N, c, t):
+    lib().orc_cnot(_state_arg(psi, N), N, c, t)
+    return psi
+
+
+def rz(psi, N, q, phi):
+    lib().orc_rz(_state_arg(psi, N), N, q, float(phi))
+    return psi
+
+
+def rx(psi, N, q, phi):
+    lib().orc_rx(_state_arg(psi, N), N, q, float(phi))
+    return psi
+
+
+# ---------------------------------------------------------------------------
+# observables (Sec. 2.4): normalised expectations, norm reported separately
+# ---------------------------------------------------------------------------
+def norm2(psi, N) -> float:
+    return lib().orc_norm2(_state_arg(psi, N), N)
+
+
+def raw_z(psi, N, links) -> float:
+    ln = np.ascontiguousarray(links, dtype=np.int32)
+    return lib().orc_expect_z(_state_arg(psi, N), N, _ip(ln), len(ln))
+
+
+def raw_x(psi, N, links) -> float:
+    ln = np.ascontiguousarray(links, dtype=np.int32)
+    return lib().orc_expect_x(_state_arg(psi, N), N, _ip(ln), len(ln))
+
+
+def expect_z(psi, N, links) -> float:
+    """<prod_{l in links} sigma^z_l>: a Wegner-Wilson loop or a plaquette U_p."""
+    return raw_z(psi, N, links) / norm2(psi, N)
+
+
+def expect_x(psi, N, links) -> float:
+    """<prod_{l in links} sigma^x_l>: a single link, a Gauss star G_i, a 't Hooft loop."""
+    return raw_x(psi, N, links) / norm2(psi, N)
+
+
+def zdos(psi, lat: Lattice) -> np.ndarray:
+    """D(z) of Sec. 3.3, indexed by m = number of odd plaquettes (z = 2m - N_p)."""
+    out = np.zeros(lat.n_plaq + 1)
+    lib().orc_zdos(_state_arg(psi, lat.N), lat.N, lat.n_plaq, _ip(lat.plaq), _dp(out))
+    return out / norm2(psi, lat.N)
+
+
+def readout(psi: np.ndarray, lat: Lattice, cx_final: float, cz_final: float) -> dict:
+    """The full readout: norm, <U_p>, <sigma^z_l>, <sigma^x_l>, <G_i>, energy.
+
+    Energy follows Sec. 2.4: <H> = -cx sum_l <sigma^x_l> - cz sum_p <U_p>.
+    """
+    N = lat.N
+    n2 = norm2(psi, N)
+    plaq = np.array([raw_z(psi, N, p) for p in lat.plaq]) / n2
+    sz = np.array([raw_z(psi, N, [q]) for q in range(N)]) / n2
+    sx = np.array([raw_x(psi, N, [q]) for q in range(N)]) / n2
+    stars = np.array([raw_x(psi, N, s) for s in lat.stars]) / n2
+    energy = -cx_final * sx.sum() - cz_final * plaq.sum()
+    return {"norm": n2, "plaq": plaq, "sigma_z": sz, "sigma_x": sx, "stars": stars,
+            "plaq_sum": plaq.sum(), "energy": energy,
+            "gauss_violation": float(np.max(np.abs(1.0 - stars)))}
+
+
+# ---------------------------------------------------------------------------
+# sampling
+# ---------------------------------------------------------------------------
+def uniform(seed: int, i: int) -> float:
+    """Draw i of the counter-based SplitMix64 stream (top 53 bits / 2^53)."""
+    return lib().orc_uniform(ctypes.c_uint64(seed), ctypes.c_uint64(i))
+
+
+def sample(psi, N, n_shots: int, seed: int) -> np.ndarray:
+    out = np.zeros(n_shots, dtype=np.uint64)
+    rc = lib().orc_sample(_state_arg(psi, N), N, n_shots, ctypes.c_uint64(seed),
+                          out.ctypes.data_as(_c_u64_p))
+    if rc != 0:
+        raise MemoryError("oracle sample")
+    return out
+
+
+def cdf(psi, N) -> np.ndarray:
+    out = np.zeros(1 << N)
+    lib().orc_cdf(_state_arg(psi, N), N, _dp(out))
+    return out
