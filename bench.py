@@ -1,0 +1,255 @@
+#!/usr/bin/env python3
+"""Benchmark: Trotterized adiabatic Z2 lattice-gauge evolution on one MI355X.
+
+One benchmark step is one complete run of the 2x2x2 (24-link) 3+1D workload:
+for each coupling lambda in {0.2, 0.5, 1.0, 2.0}, prepare |+>^24, apply 2000
+symmetric Trotter steps (T = 100, H(s) = -lambda sum sigma^x - s sum U_p,
+s ramping to 1) on the GPU in complex64, and read out the energy, every
+plaquette, the Wilson loops and the Gauss-law stars in FP64.
+
+The printed JSON line carries amp-updates/s (2^N (N_l + 1) amplitude updates
+per Trotter step), the roofline record of the dominant kernel (HIP-event
+timed inside the timed region), the oracle timed on the host cores, and the
+secondary metrics: the batched 3x3 lambda scan against the per-instance path
+and a continuous-batching serving run (p50/p99 latency, solves/s).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _lgt():
+    from paper_1910_08020_amd import lgt
+    lgt.lib()
+    return lgt
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1910_08020_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1910_08020_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def run_job(lgt, ctx, w, masks, stars_n, plaq_n):
+    """One complete workload run: every lambda, full schedule, FP64 readout."""
+    out = []
+    for lam in w.lambdas:
+        lgt.lgt_reset(ctx, lgt.LGT_INIT_PLUS, 0)
+        s = lgt.make_schedule(w.T, w.n_steps, lam, 1.0)
+        lgt.lgt_evolve(ctx, s, w.order, lgt.LGT_FORM_FUSED, 0, w.n_steps)
+        e = lgt.lgt_measure(ctx, lgt.LGT_OBS_ENERGY, cx=lam, cz=1.0)[0]
+        plaq = lgt.lgt_measure(ctx, lgt.LGT_OBS_PLAQ)[:plaq_n]
+        wl = lgt.lgt_measure(ctx, lgt.LGT_OBS_Z, masks=masks)[: len(masks)]
+        st = lgt.lgt_measure(ctx, lgt.LGT_OBS_STAR)[:stars_n]
+        out.append({"lambda": lam, "energy": float(e), "plaq_mean": float(np.mean(plaq)),
+                    "wilson": [float(x) for x in wl],
+                    "gauss_violation": float(np.max(np.abs(1 - st)))})
+    return out
+
+
+def roofline_from_stats(stats, state_bytes, traffic):
+    """Dominant pass kernel: algorithmic bytes (one read + one write of the state per
+    launch) over its mean HIP-event duration."""
+    passes = {k: v for k, v in stats.items() if k in ("pass_low", "pass_high", "small")}
+    if not passes:
+        return None
+    name, (launches, total_ms) = max(passes.items(), key=lambda kv: kv[1][1])
+    avg_s = total_ms / launches / 1e3
+    algo = 2.0 * state_bytes
+    achieved = algo / avg_s / 1e9
+    return {"bound": "hbm", "kernel": name, "launches": int(launches),
+            "avg_us": avg_s * 1e6, "bytes_per_launch": algo,
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
+
+
+def load_traffic(kernel_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel_name)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def lambda_scan(lgt, steps=None):
+    """3x3, 21 couplings, symmetric, complex64: one batched launch sequence versus
+    21 sequential per-instance runs on the same GPU."""
+    w = workloads.CONFIG2
+    n = steps or w.n_steps
+    ctxs = [lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64) for _ in w.lambdas]
+    try:
+        scheds = [lgt.make_schedule(w.T * n / w.n_steps, n, lam, 1.0) for lam in w.lambdas]
+        orders = [w.order] * len(ctxs)
+        for c in ctxs:
+            lgt.lgt_reset(c, lgt.LGT_INIT_PLUS, 0)
+        lgt.lgt_batch_evolve(ctxs, scheds, orders, 0, n)          # warm-up
+        lgt.lgt_sync(ctxs[0])
+        for c in ctxs:
+            lgt.lgt_reset(c, lgt.LGT_INIT_PLUS, 0)
+            lgt.lgt_sync(c)
+        t0 = time.perf_counter()
+        lgt.lgt_batch_evolve(ctxs, scheds, orders, 0, n)
+        for c in ctxs:
+            lgt.lgt_measure(c, lgt.LGT_OBS_PLAQ)
+        t_batch = time.perf_counter() - t0
+        for c in ctxs:
+            lgt.lgt_reset(c, lgt.LGT_INIT_PLUS, 0)
+            lgt.lgt_sync(c)
+        t0 = time.perf_counter()
+        for c, s in zip(ctxs, scheds):
+            lgt.lgt_evolve(c, s, w.order, lgt.LGT_FORM_FUSED, 0, n)
+            lgt.lgt_measure(c, lgt.LGT_OBS_PLAQ)
+        t_single = time.perf_counter() - t0
+    finally:
+        for c in ctxs:
+            lgt.lgt_destroy(c)
+    k = len(w.lambdas)
+    return {"workload": f"3x3 (18 links), {k} lambdas, {n} symmetric steps, complex64",
+            "batched_solves_per_s": k / t_batch, "per_instance_solves_per_s": k / t_single,
+            "speedup": t_single / t_batch, "batched_s": t_batch, "per_instance_s": t_single}
+
+
+def serving(lgt, n_requests, rate):
+    """Poisson stream of mixed runs through the continuous-batching server."""
+    reqs = workloads.serving_stream(n_requests, rate_per_s=rate)
+    srv = lgt.lgt_server_create(64 << 30, 64, 50)
+    tickets = []
+    try:
+        t0 = time.perf_counter()
+        for r in reqs:
+            now = time.perf_counter() - t0
+            if r.arrival_s > now:
+                time.sleep(r.arrival_s - now)
+            q = lgt.lgt_request()
+            q.d = r.d
+            for i, x in enumerate(r.L):
+                q.L[i] = x
+            q.dtype = lgt.LGT_C64
+            q.sched = lgt.make_schedule(0.05 * r.n_steps, r.n_steps, r.lam, 1.0)
+            q.order = r.order
+            tickets.append(lgt.lgt_server_submit(srv, q))
+        res = [lgt.lgt_server_wait(srv, t, 600000.0) for t in tickets]
+        wall = time.perf_counter() - t0
+    finally:
+        lgt.lgt_server_destroy(srv)
+    lat = np.array([r.latency_ms for r in res])
+    ok = sum(1 for r in res if r.status == lgt.LGT_OK)
+    return {"requests": n_requests, "offered_rate_per_s": rate, "completed_ok": ok,
+            "solves_per_s": ok / wall, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "wall_s": wall,
+            "mix": "60% 3x3, 30% 2x2x2, 10% 2x2; lambda U[0,2]; steps U{500..4000}; order 1|2"}
+
+
+def cpu_baseline(n_steps=2):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import oracle
+    lat = oracle.Lattice(3, (2, 2, 2))
+    w = workloads.CONFIG3
+    dt, cx, cz = oracle.schedule_plaquette_ramp(w.T, w.n_steps, w.lambdas[0], 1.0)
+    psi = oracle.plus_state(lat.N)
+    t0 = time.perf_counter()
+    oracle.evolve(psi, lat, dt, cx[:n_steps], cz[:n_steps], w.order)
+    el = time.perf_counter() - t0
+    upd = n_steps * (1 << lat.N) * (lat.N + 1)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": upd / el, "unit": "amp-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_steps} symmetric Trotter steps of the 2x2x2 (24-link) run at "
+                      f"lambda={w.lambdas[0]}, complex128 oracle, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this engine runs one state per GPU; only --gpus 1 is "
+                                   "measured (multi-GPU sharding is a design note)"}))
+        sys.exit(2)
+    lgt = _lgt()
+    import torch  # device and stream plumbing only
+    torch.cuda.init()
+
+    w = workloads.CONFIG3
+    ctx = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64)
+    info = lgt.lgt_info(ctx)
+    n_links, n_plaq, n_sites = info["n_links"], info["n_plaq"], info["n_sites"]
+    masks = [int(m) for m in info["plaq_masks"][:4]] + [lgt.lgt_line_mask(ctx, 0, mu)
+                                                        for mu in range(3)]
+    for _ in range(args.warmup):
+        run_job(lgt, ctx, w, masks, n_sites, n_plaq)
+    lgt.lgt_sync(ctx)
+    lgt.lgt_set_profiling(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = None
+    for _ in range(args.steps):
+        results = run_job(lgt, ctx, w, masks, n_sites, n_plaq)
+    lgt.lgt_sync(ctx)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = lgt.lgt_kernel_stats(ctx)
+    lgt.lgt_set_profiling(ctx, False)
+    state_bytes = info["state_bytes"]
+    lgt.lgt_destroy(ctx)
+
+    upd_per_job = len(w.lambdas) * w.n_steps * (1 << n_links) * (n_links + 1)
+    value = args.steps * upd_per_job / elapsed
+    roof = roofline_from_stats(stats, state_bytes, None)
+    if roof:
+        roof["traffic"] = load_traffic(roof["kernel"])
+    trotter_steps = args.steps * len(w.lambdas) * w.n_steps
+    line = {
+        "metric": "amp-updates/s", "value": value, "unit": "amp-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "2x2x2 3+1D Z2 LGT (24 links), symmetric Trotter, 2000 steps, "
+                               "T=100, lambda in {0.2,0.5,1.0,2.0}, complex64 state, FP64 readout",
+                   "trotter_steps_per_bench_step": len(w.lambdas) * w.n_steps,
+                   "us_per_trotter_step": elapsed / trotter_steps * 1e6,
+                   "algorithmic_hbm_frac_per_trotter_step":
+                       (2 * state_bytes / (HBM_PEAK_GBS * 1e9)) / (elapsed / trotter_steps),
+                   "kernel_stats_ms": {k: [int(v[0]), v[1]] for k, v in stats.items()},
+                   "readout": results},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    if not args.no_extras:
+        line["lambda_scan"] = lambda_scan(lgt)
+        line["serving"] = serving(lgt, args.serve_requests, args.serve_rate)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,311 @@
+/*
+ * lgt.h -- C ABI of the MI355X state-vector engine for the Trotterized
+ * adiabatic evolution of quantum Z2 lattice gauge theory
+ * (Cui, Shi, Yang, "Circuit-based digital adiabatic quantum simulation and
+ * pseudoquantum simulation as new approaches to lattice gauge theory",
+ * arXiv:1910.08020).
+ *
+ * Model (Sec. 2.1).  One qubit per link of a periodic d-dimensional lattice,
+ * d in {2,3}.  sigma^z|0> = |0>, sigma^z|1> = -|1>.  The engine evolves
+ *     H_j = -cx_j sum_l sigma^x_l - cz_j sum_p U_p,   U_p = prod_{l in p} sigma^z_l
+ * which covers both the paper's H = Z + g X (cx = g, cz = 1) and the form
+ * H(s) = -h_x sum sigma^x - s h_p sum U_p in which the plaquette term ramps.
+ *
+ * State layout.  2^N interleaved complex amplitudes (complex64: float re,im;
+ * complex128: double re,im), N = number of links.  Bit q of the amplitude
+ * index is link q (bit set <=> link in |1>).  Sites are numbered with the
+ * x coordinate fastest; link l(s,mu) = d*s + (d-1-mu) (mu = 0 is x); the
+ * plaquette (s; mu<nu) is {l(s,mu), l(s+e_mu,nu), l(s+e_nu,mu), l(s,nu)}.
+ * This numbering reproduces the plaquettes quoted in the caption of Fig. 1.
+ *
+ * Errors.  Every call returns an lgt_status; nothing else crosses the ABI.
+ * After a failure lgt_last_error(ctx) returns a message owned by the context
+ * (or by the library for calls without a context), valid until the next call
+ * on that context.  A context must not be used from two threads at once.
+ *
+ * Asynchrony.  Calls that enqueue GPU work (reset, evolve) return once the
+ * work is enqueued on the context's stream.  Calls that return host data
+ * (measure, sample, get_state) synchronise the stream first.
+ */
+#ifndef LGT_H
+#define LGT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lgt_ctx lgt_ctx;
+
+typedef enum {
+    LGT_OK = 0,
+    LGT_E_INVALID = 1,      /* bad argument (null pointer, size, enum, lattice) */
+    LGT_E_UNSUPPORTED = 2,  /* valid request the engine does not implement      */
+    LGT_E_OOM = 3,          /* device or host allocation failed, or over budget  */
+    LGT_E_DEVICE = 4,       /* a HIP runtime call failed                          */
+    LGT_E_STATE = 5,        /* call not valid in the object's current state       */
+    LGT_E_BUSY = 6          /* server: no slot or memory free right now           */
+} lgt_status;
+
+typedef enum { LGT_C64 = 0, LGT_C128 = 1 } lgt_dtype;
+
+/* eq. (a) generalised first-order decomposition; eq. (s) symmetric one */
+typedef enum { LGT_ORDER_TROTTER = 1, LGT_ORDER_SYMMETRIC = 2 } lgt_order;
+
+/* FUSED: link layer in LDS-tiled passes with the plaquette phases folded into
+ * the last pass.  CIRCUIT: one full-state pass per gate, as in eq. (ara)
+ * (CNOT ladder onto the last plaquette link, R_z, inverse ladder) and the
+ * R_x link layer of Sec. 2.2. */
+typedef enum { LGT_FORM_FUSED = 0, LGT_FORM_CIRCUIT = 1 } lgt_form;
+
+typedef enum {
+    LGT_INIT_PLUS = 0,     /* |+>^N: Hadamard on every link (Sec. 2.3)              */
+    LGT_INIT_ZGROUND = 1,  /* prod_p P_p |+>^N normalised: every U_p = +1 (Sec. 2.3) */
+    LGT_INIT_BASIS = 2     /* computational basis state |basis_index>                */
+} lgt_init;
+
+/* ---------------------------------------------------------------------------
+ * Lattice and context
+ * ------------------------------------------------------------------------- */
+
+/*
+ * lgt_create: build the lattice (Sec. 2.1: N_l = d prod L, N_p = N_l (d-1)/2)
+ * and allocate its 2^N_l-amplitude state on the current HIP device, set to
+ * |+>^N.  d in {2,3}; L[0..d-1] >= 2; periodic must be 1 (the paper uses tori
+ * only; 0 gives LGT_E_UNSUPPORTED).  N_l <= 34 and N_p <= 32, else
+ * LGT_E_UNSUPPORTED.  A state that does not fit gives LGT_E_OOM.
+ * On success *out owns the device state, a stream and small tables; release
+ * with lgt_destroy.
+ */
+lgt_status lgt_create(int d, const int *L, int periodic, lgt_dtype dtype, lgt_ctx **out);
+
+/*
+ * lgt_create_ex: as lgt_create, but the state lives in a caller-owned device
+ * buffer dev_buf of `bytes` bytes (>= state size, 256-byte aligned) and the
+ * context enqueues on the caller's hipStream_t `stream` (NULL: a new stream).
+ * The caller keeps ownership of both; they must outlive the context.  The
+ * buffer is set to |+>^N.
+ */
+lgt_status lgt_create_ex(int d, const int *L, int periodic, lgt_dtype dtype,
+                         void *dev_buf, size_t bytes, void *stream, lgt_ctx **out);
+
+lgt_status lgt_destroy(lgt_ctx *ctx);
+
+typedef struct {
+    int d, L[3];
+    int n_links, n_plaq, n_sites;
+    lgt_dtype dtype;
+    size_t state_bytes;
+    void *state;                  /* device pointer to the amplitudes                   */
+    void *stream;                 /* hipStream_t the context enqueues on                */
+    const uint64_t *plaq_masks;   /* [n_plaq]   links of each plaquette, as bit masks   */
+    const int32_t *plaq_links;    /* [n_plaq*4] links in the order l(s,mu), l(s+e_mu,nu), l(s+e_nu,mu), l(s,nu) */
+    const uint64_t *star_masks;   /* [n_sites]  links ending at each site (Gauss law G_i) */
+    const uint32_t *link_plaqs;   /* [n_links]  plaquettes containing each link, bit p   */
+} lgt_info_t;
+
+/* Host pointers in *out stay valid until lgt_destroy. */
+lgt_status lgt_info(const lgt_ctx *ctx, lgt_info_t *out);
+
+/*
+ * lgt_lattice_query: host-only geometry of the lattice lgt_create would build
+ * (Sec. 2.1), without touching a GPU.  Counts are written to the non-null
+ * count pointers; plaq_links (n_plaq*4 int32, same order as lgt_info) and
+ * star_masks (n_sites uint64) are filled when non-null.  Errors as lgt_create.
+ */
+lgt_status lgt_lattice_query(int d, const int *L, int *n_links, int *n_plaq, int *n_sites,
+                             int32_t *plaq_links, uint64_t *star_masks);
+
+/*
+ * lgt_wilson_mask: link mask of the boundary of a rectangular a x b region of
+ * plaquettes in the (mu,nu) plane whose lower-left corner is site `site`
+ * (a Wegner-Wilson loop, Sec. 2.1).  0 <= mu < nu < d, 1 <= a < L[mu],
+ * 1 <= b < L[nu].  With a = L[mu] the region wraps and the result is the
+ * product of two non-contractible loops.  Host-only; no GPU work.
+ */
+lgt_status lgt_wilson_mask(const lgt_ctx *ctx, int site, int mu, int nu, int a, int b,
+                           uint64_t *mask);
+
+/* lgt_line_mask: non-contractible loop C_mu through `site` (Sec. 2.1). */
+lgt_status lgt_line_mask(const lgt_ctx *ctx, int site, int mu, uint64_t *mask);
+
+/* lgt_reset: overwrite the state (Sec. 2.3). basis_index < 2^N for LGT_INIT_BASIS. */
+lgt_status lgt_reset(lgt_ctx *ctx, lgt_init init, uint64_t basis_index);
+
+/* ---------------------------------------------------------------------------
+ * Evolution (Sec. 2.2)
+ * ------------------------------------------------------------------------- */
+
+typedef enum {
+    LGT_RAMP_PLAQ = 0,      /* cx_j = h_x, cz_j = f_j h_p                           */
+    LGT_RAMP_COUPLING = 1,  /* cx_j = g0 + (g1-g0) f_j, cz_j = 1 (paper: H = Z + gX) */
+    LGT_RAMP_EXPLICIT = 2   /* cx_j = cx[j], cz_j = cz[j]                             */
+} lgt_ramp;
+
+/*
+ * Schedule of n_steps substeps of length dt = T / n_steps.  Step j
+ * (0-based) has f_j = (j+1)/n_steps when s_rule = 0: the coupling of a
+ * substep is its value at the substep's right end, as in
+ * g_{k,m} = (k-1) g_s + m delta (Sec. 2.2).  s_rule = 1 takes the midpoint
+ * (j+1/2)/n_steps.  For LGT_RAMP_EXPLICIT, cx and cz are host arrays of
+ * n_steps doubles, copied during lgt_evolve.
+ */
+typedef struct {
+    double T;
+    int64_t n_steps;
+    double h_x, h_p;
+    int ramp;
+    double g0, g1;
+    int s_rule;
+    const double *cx, *cz;
+} lgt_schedule;
+
+/*
+ * lgt_evolve: apply steps first_step .. first_step+count-1 of the schedule.
+ *   LGT_ORDER_TROTTER:   psi <- e^{-i dt Hz_j} e^{-i dt Hx_j} psi       (eq. (a))
+ *   LGT_ORDER_SYMMETRIC: psi <- e^{-i dt Hz_j/2} e^{-i dt Hx_j} e^{-i dt Hz_j/2} psi (eq. (s))
+ * with Hx_j = -cx_j sum sigma^x and Hz_j = -cz_j sum U_p.  In symmetric order
+ * the half plaquette steps of neighbouring substeps inside one call are
+ * merged into one phase (they commute, as in the rewritten product of
+ * Sec. 2.2); a call starts and ends with a half step, so splitting a run into
+ * several calls gives the same state up to rounding.  The schedule's
+ * coefficient tables are computed on the host in FP64.
+ * Errors: LGT_E_INVALID for a bad schedule or a step range outside
+ * [0, n_steps); LGT_E_UNSUPPORTED for an unknown form.
+ */
+lgt_status lgt_evolve(lgt_ctx *ctx, const lgt_schedule *sched, lgt_order order,
+                      lgt_form form, int64_t first_step, int64_t count);
+
+/* ---------------------------------------------------------------------------
+ * Pseudo-measurement (Sec. 2.4): sums over all basis states, FP64 on the GPU
+ * ------------------------------------------------------------------------- */
+
+typedef enum {
+    LGT_OBS_NORM = 0,    /* out[0] = <psi|psi>                                         */
+    LGT_OBS_Z = 1,       /* out[k] = <prod_{l in masks[k]} sigma^z_l>  (Wilson loops)   */
+    LGT_OBS_X = 2,       /* out[k] = Re<prod_{l in masks[k]} sigma^x_l> (G_i, 't Hooft) */
+    LGT_OBS_PLAQ = 3,    /* out[p] = <U_p>, p < n_plaq                                  */
+    LGT_OBS_STAR = 4,    /* out[i] = <G_i>, i < n_sites                                 */
+    LGT_OBS_SIGMAX = 5,  /* out[l] = <sigma^x_l>, l < n_links                           */
+    LGT_OBS_SIGMAZ = 6,  /* out[l] = <sigma^z_l>                                        */
+    LGT_OBS_ENERGY = 7,  /* out[0] = -cx sum_l <sigma^x_l> - cz sum_p <U_p>             */
+    LGT_OBS_ZDOS = 8     /* out[m] = weight of basis states with m odd plaquettes,
+                            i.e. Z = -sum U_p = 2m - n_plaq (Sec. 3.3), m <= n_plaq     */
+} lgt_obs_kind;
+
+typedef struct {
+    int kind;
+    int n_masks;              /* LGT_OBS_Z / LGT_OBS_X only                */
+    const uint64_t *masks;    /* host array of n_masks link masks          */
+    double cx, cz;            /* LGT_OBS_ENERGY only                       */
+} lgt_observable;
+
+/*
+ * lgt_measure: expectation values normalised by <psi|psi> (except
+ * LGT_OBS_NORM), accumulated in FP64 on the GPU, written to the host array
+ * out of out_len doubles.  out_len smaller than the result gives
+ * LGT_E_INVALID and writes nothing.
+ */
+lgt_status lgt_measure(lgt_ctx *ctx, const lgt_observable *obs, double *out, size_t out_len);
+
+/*
+ * lgt_sample: n_shots computational-basis samples written to the host array
+ * out (bit q of out[i] = link q).  Shot i draws u_i from the counter-based
+ * SplitMix64 stream (finaliser of seed + (i+1)*0x9E3779B97F4A7C15, top 53
+ * bits / 2^53) and returns the smallest b whose FP64 cumulative probability
+ * in ascending b exceeds u_i <psi|psi>.  1 <= n_shots <= 2^26.
+ */
+lgt_status lgt_sample(lgt_ctx *ctx, uint64_t n_shots, uint64_t seed, uint64_t *out);
+
+/* State transfer: host buffer of exactly info.state_bytes in the context's dtype. */
+lgt_status lgt_get_state(lgt_ctx *ctx, void *host, size_t bytes);
+lgt_status lgt_set_state(lgt_ctx *ctx, const void *host, size_t bytes);
+
+/* lgt_sync: wait for the context's stream. */
+lgt_status lgt_sync(lgt_ctx *ctx);
+
+/*
+ * lgt_kernel_stats: per kernel family, the number of launches and the summed
+ * duration measured with HIP events on the context's stream, collected while
+ * profiling is on (lgt_set_profiling).  names[i] points to a static string.
+ * Returns the number of families written (<= cap) in *n.
+ */
+lgt_status lgt_set_profiling(lgt_ctx *ctx, int on);
+lgt_status lgt_kernel_stats(lgt_ctx *ctx, const char **names, int64_t *launches,
+                            double *total_ms, int cap, int *n);
+
+/* Message for the last failure on ctx (ctx may be NULL for create/batch calls). */
+const char *lgt_last_error(const lgt_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Batching: many instances of one lattice advanced by shared launches
+ * ------------------------------------------------------------------------- */
+
+/*
+ * lgt_batch_evolve: advance n contexts that share d, L and dtype by the same
+ * step range of their own schedules (each may have its own couplings, e.g. a
+ * lambda scan).  Equivalent to calling lgt_evolve on each context, but every
+ * pass is one launch over all instances, and small lattices (N <= 12) run
+ * every step of the range in a single launch with the state held on chip.
+ * Work is enqueued on ctxs[0]'s stream; the other contexts' streams are
+ * synchronised first.  Errors as lgt_evolve; LGT_E_INVALID if the contexts do
+ * not share lattice and dtype.
+ */
+lgt_status lgt_batch_evolve(int n, lgt_ctx *const *ctxs, const lgt_schedule *scheds,
+                            const lgt_order *orders, int64_t first_step, int64_t count);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of adiabatic runs of mixed lattice sizes
+ * ------------------------------------------------------------------------- */
+
+typedef struct lgt_server lgt_server;
+
+typedef struct {
+    int d, L[3];
+    lgt_dtype dtype;
+    lgt_schedule sched;     /* cx/cz pointers, if used, are copied at submit */
+    lgt_order order;
+} lgt_request;
+
+typedef struct {
+    int done;               /* 1 when finished                                 */
+    lgt_status status;      /* LGT_OK or the failure                           */
+    double energy;          /* <H> at the last step                            */
+    double plaq_mean;       /* (1/N_p) sum_p <U_p>                             */
+    double gauss_violation; /* max_i |1 - <G_i>|                               */
+    double norm;            /* <psi|psi>                                       */
+    double latency_ms;      /* submit -> result ready                          */
+    double queue_ms;        /* submit -> admission                             */
+} lgt_result;
+
+/*
+ * lgt_server_create: a server that keeps admitted runs resident on the
+ * current device, admitting them while their state plus scratch fits in
+ * hbm_budget bytes and a slot (max_slots) is free.  A worker thread advances
+ * every admitted run by chunk_steps steps per round, one batched launch per
+ * lattice shape, so runs that arrive while others are in flight join at the
+ * next round (continuous batching).  Runs finish independently.
+ */
+lgt_status lgt_server_create(size_t hbm_budget, int max_slots, int chunk_steps,
+                             lgt_server **out);
+
+/* lgt_server_submit: queue a run; LGT_E_OOM if it can never fit the budget. */
+lgt_status lgt_server_submit(lgt_server *srv, const lgt_request *req, uint64_t *ticket);
+
+/* lgt_server_poll: non-blocking; out->done = 0 while the run is pending. */
+lgt_status lgt_server_poll(lgt_server *srv, uint64_t ticket, lgt_result *out);
+
+/* lgt_server_wait: block until the run is done (timeout_ms < 0: no limit). */
+lgt_status lgt_server_wait(lgt_server *srv, uint64_t ticket, double timeout_ms,
+                           lgt_result *out);
+
+/* lgt_server_destroy: finish in-flight runs, stop the worker, free memory. */
+lgt_status lgt_server_destroy(lgt_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LGT_H */

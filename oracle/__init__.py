@@ -320,3 +320,16 @@ def cdf(psi, N) -> np.ndarray:
     out = np.zeros(1 << N)
     lib().orc_cdf(_state_arg(psi, N), N, _dp(out))
     return out
+
+
+def zground_state(lat: Lattice) -> np.ndarray:
+    """prod_p P_p |+>^N normalised, P_p = (1 + U_p)/2 projecting on Z_p = -1 (Sec. 2.3)."""
+    N = lat.N
+    psi = plus_state(N)
+    b = np.arange(1 << N, dtype=np.int64)
+    for p in lat.plaq:
+        par = np.zeros_like(b)
+        for q in p:
+            par ^= (b >> int(q)) & 1
+        psi = 0.5 * (psi + np.where(par == 1, -1.0, 1.0) * psi)
+    return psi / np.sqrt(norm2(np.ascontiguousarray(psi), N))

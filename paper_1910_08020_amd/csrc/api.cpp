@@ -1,0 +1,839 @@
+// C ABI of the engine: contexts, evolution, pseudo-measurement, sampling,
+// batching.  See include/lgt.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lgt_internal.hpp"
+
+using namespace lgt;
+
+namespace {
+
+thread_local std::string g_err;   // errors of calls without a context
+
+struct ProfEvent {
+    int kf;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct lgt_ctx {
+    Lattice lat;
+    int dtype = LGT_C64;
+    int device = 0;
+    void *state = nullptr;
+    size_t state_bytes = 0;
+    bool own_state = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint32_t ptab[kParityBytes][256];
+    uint32_t *ptab_dev = nullptr;
+    // per-call tables (device) and their pinned staging buffer
+    void *rot_dev = nullptr, *ph_dev = nullptr;
+    size_t rot_cap = 0, ph_cap = 0;
+    void *stage = nullptr;
+    size_t stage_cap = 0;
+    hipEvent_t stage_free = nullptr;
+    DevInst *inst_dev = nullptr;
+    int inst_cap = 0;
+    // reductions
+    double *partials = nullptr;
+    uint64_t *masks_dev = nullptr;
+    std::vector<double> partials_host;
+    // profiling
+    bool profiling = false;
+    std::vector<ProfEvent> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t prof_launches[KF_COUNT] = {0};
+    double prof_ms[KF_COUNT] = {0};
+    std::string err;
+};
+
+namespace {
+
+constexpr int kMaxPartialBlocks = 2048;
+constexpr int kPartialWidth = kMaxPlaq + 1;
+constexpr int kMaskChunk = 32;
+constexpr int kFlipChunk = 8;
+
+lgt_status fail(lgt_ctx *c, lgt_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((ctx), LGT_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t elem_bytes(int dtype) { return dtype == LGT_C64 ? 8 : 16; }
+
+// grow a device buffer (stream-ordered: free after the stream drains)
+hipError_t ensure_dev(lgt_ctx *c, void **p, size_t *cap, size_t need)
+{
+    if (*cap >= need) return hipSuccess;
+    if (*p) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return e;
+        (void)hipFree(*p);
+        *p = nullptr;
+        *cap = 0;
+    }
+    size_t sz = std::max(need, (size_t)4096);
+    hipError_t e = hipMalloc(p, sz);
+    if (e == hipSuccess) *cap = sz;
+    return e;
+}
+
+hipError_t ensure_stage(lgt_ctx *c, size_t need)
+{
+    // the previous call's copies out of the staging buffer must have finished
+    hipError_t e = hipEventSynchronize(c->stage_free);
+    if (e != hipSuccess) return e;
+    if (c->stage_cap >= need) return hipSuccess;
+    if (c->stage) (void)hipHostFree(c->stage);
+    c->stage = nullptr;
+    c->stage_cap = 0;
+    size_t sz = std::max(need, (size_t)65536);
+    e = hipHostMalloc(&c->stage, sz, hipHostMallocDefault);
+    if (e == hipSuccess) c->stage_cap = sz;
+    return e;
+}
+
+// --- profiling: HIP events around launches on the context stream ----------
+hipError_t prof_begin(lgt_ctx *c, int kf, ProfEvent &pe)
+{
+    pe.kf = kf;
+    if (c->pool.size() < 2) {
+        for (int i = 0; i < 512; ++i) {
+            hipEvent_t ev;
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) return e;
+            c->pool.push_back(ev);
+        }
+    }
+    pe.a = c->pool.back(); c->pool.pop_back();
+    pe.b = c->pool.back(); c->pool.pop_back();
+    return hipEventRecord(pe.a, c->stream);
+}
+
+hipError_t prof_harvest(lgt_ctx *c)
+{
+    for (auto &pe : c->pending) {
+        hipError_t e = hipEventSynchronize(pe.b);
+        if (e != hipSuccess) return e;
+        float ms = 0;
+        e = hipEventElapsedTime(&ms, pe.a, pe.b);
+        if (e != hipSuccess) return e;
+        c->prof_launches[pe.kf] += 1;
+        c->prof_ms[pe.kf] += ms;
+        c->pool.push_back(pe.a);
+        c->pool.push_back(pe.b);
+    }
+    c->pending.clear();
+    return hipSuccess;
+}
+
+template <typename F>
+hipError_t timed(lgt_ctx *c, int kf, F &&launch)
+{
+    if (!c->profiling) return launch();
+    ProfEvent pe;
+    hipError_t e = prof_begin(c, kf, pe);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(pe.b, c->stream);
+    if (e != hipSuccess) return e;
+    c->pending.push_back(pe);
+    if (c->pending.size() >= 4096) return prof_harvest(c);
+    return hipSuccess;
+}
+
+lgt_status check_ctx(lgt_ctx *c)
+{
+    if (!c) return fail(nullptr, LGT_E_INVALID, "null context");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, LGT_E_DEVICE, "hipSetDevice failed");
+    return LGT_OK;
+}
+
+// upload rot/phase tables of one instance into dst buffers through the staging buffer
+struct Tables {
+    std::vector<RotParam<float>> rf;
+    std::vector<Cplx<float>> pf;
+    std::vector<RotParam<double>> rd;
+    std::vector<Cplx<double>> pd;
+    size_t rot_bytes = 0, ph_bytes = 0;
+};
+
+void make_tables(const Lattice &lat, int dtype, double dt, const std::vector<double> &cx,
+                 const std::vector<double> &cz, int order, StepTables &st, Tables &tb)
+{
+    build_step_tables(lat.n_links, lat.n_plaq, dt, cx.data(), cz.data(), (int)cx.size(), order, st);
+    if (dtype == LGT_C64) {
+        round_tables_f32(st, lat.n_links, lat.n_plaq, tb.rf, tb.pf);
+        tb.rot_bytes = tb.rf.size() * sizeof(RotParam<float>);
+        tb.ph_bytes = tb.pf.size() * sizeof(Cplx<float>);
+    } else {
+        round_tables_f64(st, lat.n_plaq, tb.rd, tb.pd);
+        tb.rot_bytes = tb.rd.size() * sizeof(RotParam<double>);
+        tb.ph_bytes = tb.pd.size() * sizeof(Cplx<double>);
+    }
+}
+
+const void *rot_ptr(const Tables &tb, int dtype)
+{
+    return dtype == LGT_C64 ? (const void *)tb.rf.data() : (const void *)tb.rd.data();
+}
+const void *ph_ptr(const Tables &tb, int dtype)
+{
+    return dtype == LGT_C64 ? (const void *)tb.pf.data() : (const void *)tb.pd.data();
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+namespace lgt {
+
+PassPlan plan_passes(int n_links, int dtype)
+{
+    PassPlan p;
+    if (n_links < 12) return p;   // handled on chip by the small-state kernel
+    p.low_bits = 12;
+    p.n_passes = 1;
+    int rest = n_links - 12;
+    const int hmax = dtype == LGT_C64 ? 6 : 5;
+    int nh = (rest + hmax - 1) / hmax;
+    int q = 12;
+    for (int i = 0; i < nh; ++i) {
+        int h = rest / nh + (i < rest % nh ? 1 : 0);
+        p.hi_q0[i] = q;
+        p.hi_h[i] = h;
+        q += h;
+        ++p.n_passes;
+    }
+    return p;
+}
+
+}  // namespace lgt
+
+namespace lgt {
+
+// enqueue `count` fused substeps of n_inst instances whose pointers sit in dev_inst
+hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_inst, int n_inst,
+                               int count, int pre_first, int post_off, hipStream_t st,
+                               void *prof_ctx)
+{
+    lgt_ctx *pc = (lgt_ctx *)prof_ctx;
+    auto run = [&](int kf, auto &&launch) -> hipError_t {
+        if (pc && pc->profiling) return timed(pc, kf, launch);
+        return launch();
+    };
+    if (small_supported(dtype, n)) {
+        // the small kernel reads phase[ph0] first when pre_first >= 0
+        return run(KF_SMALL, [&] {
+            return launch_small(dtype, dev_inst, n_inst, n, count, pre_first >= 0 ? 1 : 0, n_plaq, st);
+        });
+    }
+    const PassPlan plan = plan_passes(n, dtype);
+    for (int j = 0; j < count; ++j) {
+        for (int p = 0; p < plan.n_passes; ++p) {
+            const bool last = (p == plan.n_passes - 1);
+            const int post = last ? j + post_off : -1;
+            hipError_t e;
+            if (p == 0) {
+                const int pre = (j == 0) ? pre_first : -1;
+                e = run(KF_LOW, [&] {
+                    return launch_low(dtype, dev_inst, n_inst, n, plan.low_bits, j, pre, post, n_plaq, st);
+                });
+            } else {
+                e = run(KF_HIGH, [&] {
+                    return launch_high(dtype, dev_inst, n_inst, n, plan.hi_q0[p - 1], plan.hi_h[p - 1], j,
+                                       post, n_plaq, st);
+                });
+            }
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace lgt
+
+static hipError_t enqueue_fused(lgt_ctx *c, const DevInst *dev_inst, int n_inst, int count,
+                                int pre_phase)
+{
+    return enqueue_fused_steps(c->dtype, c->lat.n_links, c->lat.n_plaq, dev_inst, n_inst, count,
+                               pre_phase ? 0 : -1, pre_phase, c->stream, c);
+}
+
+static lgt_status create_common(int d, const int *L, int periodic, lgt_dtype dtype, void *buf,
+                                size_t bytes, void *stream, lgt_ctx **out)
+{
+    if (!out) return fail(nullptr, LGT_E_INVALID, "null output pointer");
+    *out = nullptr;
+    if (dtype != LGT_C64 && dtype != LGT_C128) return fail(nullptr, LGT_E_INVALID, "bad dtype");
+    if (periodic != 1)
+        return fail(nullptr, periodic == 0 ? LGT_E_UNSUPPORTED : LGT_E_INVALID,
+                    "only periodic lattices (tori) are supported");
+    Lattice lat;
+    std::string why = build_lattice(d, L, lat);
+    if (!why.empty()) {
+        bool unsup = why.find("too many") != std::string::npos;
+        return fail(nullptr, unsup ? LGT_E_UNSUPPORTED : LGT_E_INVALID, why);
+    }
+    std::unique_ptr<lgt_ctx> c(new (std::nothrow) lgt_ctx());
+    if (!c) return fail(nullptr, LGT_E_OOM, "host allocation failed");
+    c->lat = std::move(lat);
+    c->dtype = dtype;
+    c->state_bytes = ((size_t)1 << c->lat.n_links) * elem_bytes(dtype);
+    if (hipGetDevice(&c->device) != hipSuccess) return fail(nullptr, LGT_E_DEVICE, "no HIP device");
+    if (buf) {
+        if (bytes < c->state_bytes) return fail(nullptr, LGT_E_INVALID, "external buffer too small");
+        if ((uintptr_t)buf % 256) return fail(nullptr, LGT_E_INVALID, "external buffer not 256-byte aligned");
+        c->state = buf;
+    } else {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && c->state_bytes + (64u << 20) > free_b)
+            return fail(nullptr, LGT_E_OOM, "state does not fit in free device memory");
+        if (hipMalloc(&c->state, c->state_bytes) != hipSuccess)
+            return fail(nullptr, LGT_E_OOM, "hipMalloc of the state failed");
+        c->own_state = true;
+    }
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            lgt_destroy(c.release());
+            return fail(nullptr, LGT_E_DEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    build_parity_tables(c->lat, c->ptab);
+    lgt_ctx *raw = c.get();
+    auto bail = [&](const char *m) {
+        lgt_destroy(c.release());
+        return fail(nullptr, LGT_E_DEVICE, m);
+    };
+    if (hipMalloc((void **)&raw->ptab_dev, sizeof(raw->ptab)) != hipSuccess) return bail("hipMalloc tables");
+    if (hipMemcpy(raw->ptab_dev, raw->ptab, sizeof(raw->ptab), hipMemcpyHostToDevice) != hipSuccess)
+        return bail("upload tables");
+    if (hipMalloc((void **)&raw->partials, sizeof(double) * kMaxPartialBlocks * kPartialWidth) != hipSuccess)
+        return bail("hipMalloc partials");
+    if (hipMalloc((void **)&raw->masks_dev, sizeof(uint64_t) * 64) != hipSuccess) return bail("hipMalloc masks");
+    if (hipEventCreateWithFlags(&raw->stage_free, hipEventDisableTiming) != hipSuccess) return bail("event");
+    if (hipEventRecord(raw->stage_free, raw->stream) != hipSuccess) return bail("event record");
+    raw->partials_host.resize((size_t)kMaxPartialBlocks * kPartialWidth);
+    lgt_status s = lgt_reset(raw, LGT_INIT_PLUS, 0);
+    if (s != LGT_OK) {
+        std::string m = raw->err;
+        lgt_destroy(c.release());
+        return fail(nullptr, s, m);
+    }
+    *out = c.release();
+    return LGT_OK;
+}
+
+extern "C" {
+
+lgt_status lgt_create(int d, const int *L, int periodic, lgt_dtype dtype, lgt_ctx **out)
+{
+    return create_common(d, L, periodic, dtype, nullptr, 0, nullptr, out);
+}
+
+lgt_status lgt_create_ex(int d, const int *L, int periodic, lgt_dtype dtype, void *dev_buf,
+                         size_t bytes, void *stream, lgt_ctx **out)
+{
+    if (!dev_buf) return fail(nullptr, LGT_E_INVALID, "null device buffer");
+    return create_common(d, L, periodic, dtype, dev_buf, bytes, stream, out);
+}
+
+lgt_status lgt_destroy(lgt_ctx *c)
+{
+    if (!c) return LGT_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto &pe : c->pending) {
+        (void)hipEventDestroy(pe.a);
+        (void)hipEventDestroy(pe.b);
+    }
+    for (auto ev : c->pool) (void)hipEventDestroy(ev);
+    if (c->own_state && c->state) (void)hipFree(c->state);
+    if (c->ptab_dev) (void)hipFree(c->ptab_dev);
+    if (c->rot_dev) (void)hipFree(c->rot_dev);
+    if (c->ph_dev) (void)hipFree(c->ph_dev);
+    if (c->inst_dev) (void)hipFree(c->inst_dev);
+    if (c->partials) (void)hipFree(c->partials);
+    if (c->masks_dev) (void)hipFree(c->masks_dev);
+    if (c->stage) (void)hipHostFree(c->stage);
+    if (c->stage_free) (void)hipEventDestroy(c->stage_free);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return LGT_OK;
+}
+
+lgt_status lgt_info(const lgt_ctx *c, lgt_info_t *o)
+{
+    if (!c || !o) return fail(nullptr, LGT_E_INVALID, "null argument");
+    const Lattice &l = c->lat;
+    o->d = l.d;
+    for (int i = 0; i < 3; ++i) o->L[i] = i < l.d ? l.L[i] : 1;
+    o->n_links = l.n_links;
+    o->n_plaq = l.n_plaq;
+    o->n_sites = l.n_sites;
+    o->dtype = (lgt_dtype)c->dtype;
+    o->state_bytes = c->state_bytes;
+    o->state = c->state;
+    o->stream = c->stream;
+    o->plaq_masks = l.plaq_mask.data();
+    o->plaq_links = l.plaq_links.data();
+    o->star_masks = l.star_mask.data();
+    o->link_plaqs = l.link_plaqs.data();
+    return LGT_OK;
+}
+
+lgt_status lgt_lattice_query(int d, const int *L, int *n_links, int *n_plaq, int *n_sites,
+                             int32_t *plaq_links, uint64_t *star_masks)
+{
+    Lattice lat;
+    std::string why = build_lattice(d, L, lat);
+    if (!why.empty())
+        return fail(nullptr, why.find("too many") != std::string::npos ? LGT_E_UNSUPPORTED : LGT_E_INVALID, why);
+    if (n_links) *n_links = lat.n_links;
+    if (n_plaq) *n_plaq = lat.n_plaq;
+    if (n_sites) *n_sites = lat.n_sites;
+    if (plaq_links) std::memcpy(plaq_links, lat.plaq_links.data(), sizeof(int32_t) * lat.plaq_links.size());
+    if (star_masks) std::memcpy(star_masks, lat.star_mask.data(), sizeof(uint64_t) * lat.star_mask.size());
+    return LGT_OK;
+}
+
+lgt_status lgt_wilson_mask(const lgt_ctx *c, int site, int mu, int nu, int a, int b, uint64_t *mask)
+{
+    if (!c || !mask) return fail(nullptr, LGT_E_INVALID, "null argument");
+    const Lattice &l = c->lat;
+    if (site < 0 || site >= l.n_sites || mu < 0 || nu <= mu || nu >= l.d || a < 1 || b < 1 ||
+        a > l.L[mu] || b > l.L[nu])
+        return fail(const_cast<lgt_ctx *>(c), LGT_E_INVALID, "bad Wilson loop geometry");
+    *mask = region_mask(l, site, mu, nu, a, b);
+    return LGT_OK;
+}
+
+lgt_status lgt_line_mask(const lgt_ctx *c, int site, int mu, uint64_t *mask)
+{
+    if (!c || !mask) return fail(nullptr, LGT_E_INVALID, "null argument");
+    if (site < 0 || site >= c->lat.n_sites || mu < 0 || mu >= c->lat.d)
+        return fail(const_cast<lgt_ctx *>(c), LGT_E_INVALID, "bad line");
+    *mask = line_mask(c->lat, site, mu);
+    return LGT_OK;
+}
+
+lgt_status lgt_reset(lgt_ctx *c, lgt_init init, uint64_t basis_index)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    const int n = c->lat.n_links;
+    double amp = 0;
+    if (init == LGT_INIT_PLUS) {
+        amp = std::ldexp(1.0, -n / 2) * ((n & 1) ? std::sqrt(0.5) : 1.0);
+    } else if (init == LGT_INIT_BASIS) {
+        if (basis_index >> n) return fail(c, LGT_E_INVALID, "basis index >= 2^N");
+    } else if (init == LGT_INIT_ZGROUND) {
+        // uniform superposition of the 2^(N - rank) basis states with every U_p = +1
+        std::vector<uint64_t> rows(c->lat.plaq_mask);
+        int rank = 0;
+        for (int bit = 0; bit < n; ++bit) {
+            auto it = std::find_if(rows.begin(), rows.end(), [&](uint64_t r) { return (r >> bit) & 1; });
+            if (it == rows.end()) continue;
+            uint64_t piv = *it;
+            rows.erase(it);
+            for (auto &r : rows)
+                if ((r >> bit) & 1) r ^= piv;
+            ++rank;
+        }
+        const int k = n - rank;
+        amp = std::ldexp(1.0, -k / 2) * ((k & 1) ? std::sqrt(0.5) : 1.0);
+    } else {
+        return fail(c, LGT_E_INVALID, "bad init kind");
+    }
+    HIPCHK(c, timed(c, KF_INIT, [&] {
+        return launch_init(c->dtype, c->state, n, init, basis_index, amp, c->ptab_dev, c->stream);
+    }));
+    return LGT_OK;
+}
+
+lgt_status lgt_evolve(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, lgt_form form,
+                      int64_t first_step, int64_t count)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (order != LGT_ORDER_TROTTER && order != LGT_ORDER_SYMMETRIC)
+        return fail(c, LGT_E_INVALID, "bad order");
+    if (form != LGT_FORM_FUSED && form != LGT_FORM_CIRCUIT)
+        return fail(c, LGT_E_UNSUPPORTED, "unknown form");
+    double dt = 0;
+    std::vector<double> cx, cz;
+    std::string why = schedule_coeffs(sched, first_step, count, dt, cx, cz);
+    if (!why.empty()) return fail(c, LGT_E_INVALID, why);
+    if (count == 0) return LGT_OK;
+    const Lattice &lat = c->lat;
+    const int n = lat.n_links;
+    StepTables st;
+    if (form == LGT_FORM_CIRCUIT) {
+        // one pass per gate; the symmetric order merges neighbouring half steps
+        // like the fused path (rewritten product after eq. (s))
+        build_step_tables(n, lat.n_plaq, dt, cx.data(), cz.data(), (int)count, order, st);
+        std::vector<double> theta(st.n_phase);
+        if (order == LGT_ORDER_TROTTER) {
+            for (int64_t j = 0; j < count; ++j) theta[j] = dt * cz[j];
+        } else {
+            theta[0] = 0.5 * dt * cz[0];
+            for (int64_t j = 0; j < count; ++j)
+                theta[j + 1] = (j + 1 < count) ? 0.5 * dt * (cz[j] + cz[j + 1]) : 0.5 * dt * cz[j];
+        }
+        auto gadgets = [&](double th) -> hipError_t {
+            for (int p = 0; p < lat.n_plaq; ++p) {
+                const int32_t *l = &lat.plaq_links[4 * p];
+                const int tq = l[3];
+                for (int k = 0; k < 3; ++k) {
+                    hipError_t e = timed(c, KF_GATE_CNOT, [&] { return launch_gate_cnot(c->dtype, c->state, n, l[k], tq, c->stream); });
+                    if (e != hipSuccess) return e;
+                }
+                hipError_t e = timed(c, KF_GATE_RZ, [&] { return launch_gate_rz(c->dtype, c->state, n, tq, -2.0 * th, c->stream); });
+                if (e != hipSuccess) return e;
+                for (int k = 2; k >= 0; --k) {
+                    e = timed(c, KF_GATE_CNOT, [&] { return launch_gate_cnot(c->dtype, c->state, n, l[k], tq, c->stream); });
+                    if (e != hipSuccess) return e;
+                }
+            }
+            return hipSuccess;
+        };
+        const int pre = st.pre_phase;
+        if (pre) HIPCHK(c, gadgets(theta[0]));
+        for (int64_t j = 0; j < count; ++j) {
+            const double alpha = dt * cx[j];
+            for (int q = 0; q < n; ++q)
+                HIPCHK(c, timed(c, KF_GATE_RX, [&] { return launch_gate_rx(c->dtype, c->state, n, q, -2.0 * alpha, c->stream); }));
+            HIPCHK(c, gadgets(theta[j + pre]));
+        }
+        return LGT_OK;
+    }
+    if (count > (1 << 24)) return fail(c, LGT_E_INVALID, "too many steps in one call");
+    Tables tb;
+    make_tables(lat, c->dtype, dt, cx, cz, order, st, tb);
+    const size_t rb = align256(tb.rot_bytes), pb = align256(tb.ph_bytes);
+    HIPCHK(c, ensure_stage(c, rb + pb + 256));
+    HIPCHK(c, ensure_dev(c, &c->rot_dev, &c->rot_cap, rb));
+    HIPCHK(c, ensure_dev(c, &c->ph_dev, &c->ph_cap, pb));
+    if (c->inst_cap < 1) {
+        void *p = c->inst_dev;
+        size_t cap = 0;
+        HIPCHK(c, ensure_dev(c, &p, &cap, sizeof(DevInst)));
+        c->inst_dev = (DevInst *)p;
+        c->inst_cap = 1;
+    }
+    char *stg = (char *)c->stage;
+    std::memcpy(stg, rot_ptr(tb, c->dtype), tb.rot_bytes);
+    std::memcpy(stg + rb, ph_ptr(tb, c->dtype), tb.ph_bytes);
+    DevInst di{};
+    di.psi = c->state;
+    di.rot = c->rot_dev;
+    di.phase = c->ph_dev;
+    di.ptab = c->ptab_dev;
+    di.step0 = 0;
+    di.ph0 = 0;
+    di.n_total = (int)count;
+    std::memcpy(stg + rb + pb, &di, sizeof(di));
+    HIPCHK(c, hipMemcpyAsync(c->rot_dev, stg, tb.rot_bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ph_dev, stg + rb, tb.ph_bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->inst_dev, stg + rb + pb, sizeof(DevInst), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipEventRecord(c->stage_free, c->stream));
+    HIPCHK(c, enqueue_fused(c, c->inst_dev, 1, (int)count, st.pre_phase));
+    return LGT_OK;
+}
+
+static lgt_status reduce_masks(lgt_ctx *c, bool flip, const uint64_t *masks, int n_masks,
+                               std::vector<long double> &out)
+{
+    const int n = c->lat.n_links;
+    const int chunk = flip ? kFlipChunk : kMaskChunk;
+    const int g = reduce_blocks(n);
+    out.assign(n_masks, 0.0L);
+    for (int k0 = 0; k0 < n_masks; k0 += chunk) {
+        const int m = std::min(chunk, n_masks - k0);
+        HIPCHK(c, hipMemcpyAsync(c->masks_dev, masks + k0, sizeof(uint64_t) * m,
+                                 hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, timed(c, flip ? KF_RED_FLIP : KF_RED_DIAG, [&] {
+            return flip ? launch_reduce_flip(c->dtype, c->state, n, c->masks_dev, m, c->partials, c->stream)
+                        : launch_reduce_diag(c->dtype, c->state, n, c->masks_dev, m, c->partials, c->stream);
+        }));
+        HIPCHK(c, hipMemcpyAsync(c->partials_host.data(), c->partials, sizeof(double) * g * chunk,
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int i = 0; i < m; ++i) {
+            long double acc = 0;
+            for (int b = 0; b < g; ++b) acc += c->partials_host[(size_t)b * chunk + i];
+            out[k0 + i] = acc;
+        }
+    }
+    return LGT_OK;
+}
+
+static lgt_status norm_of(lgt_ctx *c, long double &nrm)
+{
+    uint64_t zero = 0;
+    std::vector<long double> v;
+    lgt_status s = reduce_masks(c, false, &zero, 1, v);
+    if (s) return s;
+    nrm = v[0];
+    return LGT_OK;
+}
+
+lgt_status lgt_measure(lgt_ctx *c, const lgt_observable *obs, double *out, size_t out_len)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (!obs || !out) return fail(c, LGT_E_INVALID, "null argument");
+    const Lattice &lat = c->lat;
+    std::vector<uint64_t> masks;
+    bool flip = false;
+    size_t need = 0;
+    switch (obs->kind) {
+    case LGT_OBS_NORM: need = 1; break;
+    case LGT_OBS_Z:
+    case LGT_OBS_X:
+        if (obs->n_masks < 1 || !obs->masks) return fail(c, LGT_E_INVALID, "need masks");
+        for (int i = 0; i < obs->n_masks; ++i)
+            if (obs->masks[i] >> lat.n_links) return fail(c, LGT_E_INVALID, "mask has bits beyond N");
+        masks.assign(obs->masks, obs->masks + obs->n_masks);
+        flip = obs->kind == LGT_OBS_X;
+        need = masks.size();
+        break;
+    case LGT_OBS_PLAQ: masks = lat.plaq_mask; need = masks.size(); break;
+    case LGT_OBS_STAR: masks = lat.star_mask; flip = true; need = masks.size(); break;
+    case LGT_OBS_SIGMAX:
+    case LGT_OBS_SIGMAZ:
+        for (int q = 0; q < lat.n_links; ++q) masks.push_back(1ull << q);
+        flip = obs->kind == LGT_OBS_SIGMAX;
+        need = masks.size();
+        break;
+    case LGT_OBS_ENERGY: need = 1; break;
+    case LGT_OBS_ZDOS: need = lat.n_plaq + 1; break;
+    default: return fail(c, LGT_E_INVALID, "unknown observable");
+    }
+    if (out_len < need) return fail(c, LGT_E_INVALID, "output array too short");
+    long double nrm = 0;
+    if ((s = norm_of(c, nrm))) return s;
+    if (obs->kind == LGT_OBS_NORM) {
+        out[0] = (double)nrm;
+        return LGT_OK;
+    }
+    if (!(nrm > 0)) return fail(c, LGT_E_STATE, "state has zero norm");
+    if (obs->kind == LGT_OBS_ZDOS) {
+        const int g = reduce_blocks(lat.n_links);
+        HIPCHK(c, timed(c, KF_RED_DOS, [&] {
+            return launch_reduce_dos(c->dtype, c->state, lat.n_links, c->ptab_dev, lat.n_plaq, c->partials, c->stream);
+        }));
+        HIPCHK(c, hipMemcpyAsync(c->partials_host.data(), c->partials, sizeof(double) * g * kPartialWidth,
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int m = 0; m <= lat.n_plaq; ++m) {
+            long double acc = 0;
+            for (int b = 0; b < g; ++b) acc += c->partials_host[(size_t)b * kPartialWidth + m];
+            out[m] = (double)(acc / nrm);
+        }
+        return LGT_OK;
+    }
+    if (obs->kind == LGT_OBS_ENERGY) {
+        std::vector<uint64_t> sx;
+        for (int q = 0; q < lat.n_links; ++q) sx.push_back(1ull << q);
+        std::vector<long double> vx, vz;
+        if ((s = reduce_masks(c, true, sx.data(), (int)sx.size(), vx))) return s;
+        if ((s = reduce_masks(c, false, lat.plaq_mask.data(), lat.n_plaq, vz))) return s;
+        long double ex = 0, ez = 0;
+        for (auto v : vx) ex += v;
+        for (auto v : vz) ez += v;
+        out[0] = (double)((-(long double)obs->cx * ex - (long double)obs->cz * ez) / nrm);
+        return LGT_OK;
+    }
+    std::vector<long double> v;
+    if ((s = reduce_masks(c, flip, masks.data(), (int)masks.size(), v))) return s;
+    for (size_t i = 0; i < masks.size(); ++i) out[i] = (double)(v[i] / nrm);
+    return LGT_OK;
+}
+
+lgt_status lgt_sample(lgt_ctx *c, uint64_t n_shots, uint64_t seed, uint64_t *out)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (!out) return fail(c, LGT_E_INVALID, "null output");
+    if (n_shots < 1 || n_shots > (1ull << 26)) return fail(c, LGT_E_INVALID, "n_shots out of range");
+    const int n = c->lat.n_links;
+    const size_t nb = (size_t)1 << (n - sample_block_bits(n));
+    double *sums = nullptr, *prefix = nullptr;
+    uint64_t *dev_out = nullptr;
+    auto cleanup = [&] {
+        if (sums) (void)hipFree(sums);
+        if (prefix) (void)hipFree(prefix);
+        if (dev_out) (void)hipFree(dev_out);
+    };
+    if (hipMalloc((void **)&sums, nb * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&prefix, nb * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&dev_out, n_shots * sizeof(uint64_t)) != hipSuccess) {
+        cleanup();
+        return fail(c, LGT_E_OOM, "sampling buffers");
+    }
+    hipError_t e = timed(c, KF_SAMPLE, [&] {
+        return launch_sample(c->dtype, c->state, n, n_shots, seed, sums, prefix, dev_out, c->stream);
+    });
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dev_out, n_shots * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    cleanup();
+    if (e != hipSuccess) return fail(c, LGT_E_DEVICE, std::string("sample: ") + hipGetErrorString(e));
+    return LGT_OK;
+}
+
+lgt_status lgt_get_state(lgt_ctx *c, void *host, size_t bytes)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (!host || bytes != c->state_bytes) return fail(c, LGT_E_INVALID, "host buffer must be state_bytes");
+    HIPCHK(c, hipMemcpyAsync(host, c->state, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LGT_OK;
+}
+
+lgt_status lgt_set_state(lgt_ctx *c, const void *host, size_t bytes)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (!host || bytes != c->state_bytes) return fail(c, LGT_E_INVALID, "host buffer must be state_bytes");
+    HIPCHK(c, hipMemcpyAsync(c->state, host, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LGT_OK;
+}
+
+lgt_status lgt_sync(lgt_ctx *c)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LGT_OK;
+}
+
+lgt_status lgt_set_profiling(lgt_ctx *c, int on)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    HIPCHK(c, prof_harvest(c));
+    c->profiling = on != 0;
+    for (int k = 0; k < KF_COUNT; ++k) {
+        c->prof_launches[k] = 0;
+        c->prof_ms[k] = 0;
+    }
+    return LGT_OK;
+}
+
+lgt_status lgt_kernel_stats(lgt_ctx *c, const char **names, int64_t *launches, double *total_ms,
+                            int cap, int *n)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (!n) return fail(c, LGT_E_INVALID, "null count");
+    HIPCHK(c, prof_harvest(c));
+    int k = 0;
+    for (int f = 0; f < KF_COUNT && k < cap; ++f) {
+        if (!c->prof_launches[f]) continue;
+        if (names) names[k] = kernel_family_name(f);
+        if (launches) launches[k] = c->prof_launches[f];
+        if (total_ms) total_ms[k] = c->prof_ms[f];
+        ++k;
+    }
+    *n = k;
+    return LGT_OK;
+}
+
+const char *lgt_last_error(const lgt_ctx *c)
+{
+    return c ? c->err.c_str() : g_err.c_str();
+}
+
+lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule *scheds,
+                            const lgt_order *orders, int64_t first_step, int64_t count)
+{
+    if (n_inst < 1 || !ctxs || !scheds || !orders) return fail(nullptr, LGT_E_INVALID, "bad batch arguments");
+    lgt_ctx *c0 = ctxs[0];
+    if (!c0) return fail(nullptr, LGT_E_INVALID, "null context in batch");
+    if (n_inst > 65535) return fail(nullptr, LGT_E_INVALID, "too many instances");
+    for (int i = 0; i < n_inst; ++i) {
+        lgt_ctx *c = ctxs[i];
+        if (!c || c->dtype != c0->dtype || c->lat.d != c0->lat.d ||
+            std::memcmp(c->lat.L, c0->lat.L, sizeof c->lat.L) != 0 || c->device != c0->device)
+            return fail(nullptr, LGT_E_INVALID, "batch contexts must share lattice, dtype and device");
+        if (orders[i] != LGT_ORDER_TROTTER && orders[i] != LGT_ORDER_SYMMETRIC)
+            return fail(nullptr, LGT_E_INVALID, "bad order");
+        if (orders[i] != orders[0])
+            return fail(nullptr, LGT_E_UNSUPPORTED, "batched instances must share the order");
+    }
+    lgt_status s = check_ctx(c0);
+    if (s) return fail(nullptr, s, c0->err);
+    if (count == 0) return LGT_OK;
+    // every instance's tables in one staging block
+    std::vector<Tables> tbs(n_inst);
+    StepTables st;
+    for (int i = 0; i < n_inst; ++i) {
+        double dt;
+        std::vector<double> cx, cz;
+        std::string why = schedule_coeffs(&scheds[i], first_step, count, dt, cx, cz);
+        if (!why.empty()) return fail(nullptr, LGT_E_INVALID, why);
+        make_tables(c0->lat, c0->dtype, dt, cx, cz, orders[i], st, tbs[i]);
+    }
+    const size_t rb = align256(tbs[0].rot_bytes), pb = align256(tbs[0].ph_bytes);
+    const size_t ib = align256(sizeof(DevInst) * n_inst);
+    const size_t total = (rb + pb) * n_inst + ib;
+    for (int i = 1; i < n_inst; ++i)
+        if (ctxs[i]->stream != c0->stream && hipStreamSynchronize(ctxs[i]->stream) != hipSuccess)
+            return fail(nullptr, LGT_E_DEVICE, "sync of a batch member failed");
+    if (ensure_stage(c0, total) != hipSuccess) return fail(nullptr, LGT_E_OOM, "staging buffer");
+    if (ensure_dev(c0, &c0->rot_dev, &c0->rot_cap, total) != hipSuccess)
+        return fail(nullptr, LGT_E_OOM, "batch tables");
+    char *stg = (char *)c0->stage;
+    char *dev = (char *)c0->rot_dev;
+    std::vector<DevInst> di(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        std::memcpy(stg + i * (rb + pb), rot_ptr(tbs[i], c0->dtype), tbs[i].rot_bytes);
+        std::memcpy(stg + i * (rb + pb) + rb, ph_ptr(tbs[i], c0->dtype), tbs[i].ph_bytes);
+        di[i].psi = ctxs[i]->state;
+        di[i].rot = dev + i * (rb + pb);
+        di[i].phase = dev + i * (rb + pb) + rb;
+        di[i].ptab = c0->ptab_dev;
+        di[i].step0 = 0;
+        di[i].ph0 = 0;
+        di[i].n_total = (int)count;
+    }
+    std::memcpy(stg + (rb + pb) * n_inst, di.data(), sizeof(DevInst) * n_inst);
+    if (hipMemcpyAsync(dev, stg, total, hipMemcpyHostToDevice, c0->stream) != hipSuccess ||
+        hipEventRecord(c0->stage_free, c0->stream) != hipSuccess)
+        return fail(nullptr, LGT_E_DEVICE, "batch upload");
+    hipError_t e = enqueue_fused(c0, (const DevInst *)(dev + (rb + pb) * n_inst), n_inst, (int)count, st.pre_phase);
+    if (e != hipSuccess) return fail(nullptr, LGT_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+    // the other contexts must not race ahead of the shared launches
+    for (int i = 1; i < n_inst; ++i)
+        if (ctxs[i]->stream != c0->stream && hipStreamSynchronize(c0->stream) != hipSuccess)
+            return fail(nullptr, LGT_E_DEVICE, "batch sync");
+    return LGT_OK;
+}
+
+}  // extern "C"

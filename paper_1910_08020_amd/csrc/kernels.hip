@@ -1,0 +1,774 @@
+// HIP kernels for the Trotterized Z2 lattice-gauge state vector on CDNA4 (gfx950).
+//
+// One Trotter substep (Sec. 2.2 of arXiv:1910.08020) is a link layer
+// prod_l exp(i a sigma^x_l) followed by the diagonal plaquette phase
+// exp(i theta sum_p U_p).  The link layer is a tensor product of identical
+// 2x2 rotations, applied in a few passes over HBM:
+//   * low pass: a contiguous tile of 2^12 amplitudes staged through LDS, all
+//     twelve low link qubits rotated in registers between LDS transposes;
+//   * high passes: each lane keeps 2^h amplitudes that differ in h higher
+//     link qubits in registers, with lanes of a wave on consecutive
+//     amplitudes, so every load instruction reads one contiguous segment.
+// The plaquette phase is folded into the last pass: the plaquette syndrome
+// P(b) (bit p = parity of plaquette p on basis state b) is linear over GF(2),
+// so P(base | r) = P(base) ^ P(r) with P(base) from byte tables in LDS and
+// P(r) from the per-link plaquette sets; the phase is table[popcount(P)].
+#include <hip/hip_runtime.h>
+
+#include "lgt_internal.hpp"
+
+namespace lgt {
+
+template <typename T> struct CV;
+template <> struct CV<float> { using type = float2; };
+template <> struct CV<double> { using type = double2; };
+
+template <typename T>
+using cplx_t = typename CV<T>::type;
+
+constexpr int kPtabWords = kParityBytes * 256;
+
+__device__ __forceinline__ uint32_t syndrome(uint64_t b, const uint32_t *tab)
+{
+    return tab[(uint32_t)b & 255u] ^ tab[256 + (((uint32_t)b >> 8) & 255u)] ^
+           tab[512 + (((uint32_t)b >> 16) & 255u)] ^ tab[768 + (((uint32_t)b >> 24) & 255u)] ^
+           tab[1024 + ((uint32_t)(b >> 32) & 255u)];
+}
+
+// plaquettes touching link q, read from the byte tables (single-bit entry)
+__device__ __forceinline__ uint32_t link_set(int q, const uint32_t *tab)
+{
+    return tab[(q >> 3) * 256 + (1 << (q & 7))];
+}
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b)
+{
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+// (a0, a1) <- (u a0 + i v a1, i v a0 + u a1): the link rotation up to the scale
+// folded into the phase table.  One of u, v is exactly 1.
+template <typename T, typename C>
+__device__ __forceinline__ void rot_pair(C &a0, C &a1, T u, T v)
+{
+    C b0, b1;
+    b0.x = u * a0.x - v * a1.y;
+    b0.y = u * a0.y + v * a1.x;
+    b1.x = u * a1.x - v * a0.y;
+    b1.y = u * a1.y + v * a0.x;
+    a0 = b0;
+    a1 = b1;
+}
+
+// rotate every register bit of a 2^B register array
+template <typename T, typename C, int B>
+__device__ __forceinline__ void rot_regs(C *v, T u, T w)
+{
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+#pragma unroll
+        for (int r = 0; r < (1 << B); ++r)
+            if (!(r & (1 << k))) rot_pair<T, C>(v[r], v[r | (1 << k)], u, w);
+}
+
+// multiply a 2^B register array (register r <-> global index base | sum_k r_k 2^{q_k})
+// by table[popcount(P0 ^ P(r))], qs holding the plaquette sets of the register bits
+template <typename C, int B>
+__device__ __forceinline__ void apply_phase_regs(C *v, uint32_t P0, const uint32_t *qs,
+                                                 const C *table)
+{
+#pragma unroll
+    for (int r = 0; r < (1 << B); ++r) {
+        uint32_t P = P0;
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (r & (1 << k)) P ^= qs[k];
+        v[r] = cmul(v[r], table[__popc(P)]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_tables(const DevInst &in, int n_plaq, int pre, int post,
+                                            uint32_t *ptab, cplx_t<T> *ph_pre,
+                                            cplx_t<T> *ph_post)
+{
+    using C = cplx_t<T>;
+    for (int i = threadIdx.x; i < kPtabWords; i += blockDim.x) ptab[i] = in.ptab[i];
+    const C *ph = (const C *)in.phase;
+    const int np1 = n_plaq + 1;
+    if (pre >= 0)
+        for (int i = threadIdx.x; i < np1; i += blockDim.x)
+            ph_pre[i] = ph[(size_t)(in.ph0 + pre) * np1 + i];
+    if (post >= 0)
+        for (int i = threadIdx.x; i < np1; i += blockDim.x)
+            ph_post[i] = ph[(size_t)(in.ph0 + post) * np1 + i];
+}
+
+// ---------------------------------------------------------------------------
+// low pass: tile of 4096 contiguous amplitudes, 256 threads x 16 registers
+// ---------------------------------------------------------------------------
+constexpr int kLowBits = 12;
+constexpr int kLowThreads = 256;
+
+// LDS address swizzle: flips bits 0..3 by bits 4..7 and bit 4 by bit 8, so the
+// three access patterns below hit distinct banks within each half wave.
+__device__ __forceinline__ int swz(int i) { return i ^ ((i >> 4) & 15) ^ (((i >> 8) & 1) << 4); }
+
+template <typename T>
+__global__ __launch_bounds__(kLowThreads) void k_low(const DevInst *__restrict__ insts, int step,
+                                                     int pre, int post, int n_plaq)
+{
+    using C = cplx_t<T>;
+    __shared__ C buf[1 << kLowBits];
+    __shared__ uint32_t ptab[kPtabWords];
+    __shared__ C ph_pre[kMaxPlaq + 1], ph_post[kMaxPlaq + 1];
+
+    const DevInst in = insts[blockIdx.y];
+    if (in.step0 + step >= in.n_total) return;   // instance already finished (uniform per block)
+    C *__restrict__ psi = (C *)in.psi;
+    const int t = threadIdx.x;
+    const uint64_t base = (uint64_t)blockIdx.x << kLowBits;
+    const RotParam<T> rp = ((const RotParam<T> *)in.rot)[in.step0 + step];
+    load_tables<T>(in, n_plaq, pre, post, ptab, ph_pre, ph_post);
+    __syncthreads();
+
+    C v[16];
+    // round 1: registers hold tile bits 8..11, coalesced loads
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = psi[base + t + (r << 8)];
+    if (pre >= 0) {
+        uint32_t qs[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) qs[k] = link_set(8 + k, ptab);
+        apply_phase_regs<C, 4>(v, syndrome(base + t, ptab), qs, ph_pre);
+    }
+    rot_regs<T, C, 4>(v, rp.u, rp.v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) buf[swz(t + (r << 8))] = v[r];
+    __syncthreads();
+    // round 2: registers hold tile bits 4..7
+    const int i2 = (t & 15) | ((t >> 4) << 8);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = buf[swz(i2 | (r << 4))];
+    rot_regs<T, C, 4>(v, rp.u, rp.v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) buf[swz(i2 | (r << 4))] = v[r];
+    __syncthreads();
+    // round 3: registers hold tile bits 0..3
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = buf[swz(r | (t << 4))];
+    rot_regs<T, C, 4>(v, rp.u, rp.v);
+    if (post >= 0) {
+        uint32_t qs[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) qs[k] = link_set(k, ptab);
+        apply_phase_regs<C, 4>(v, syndrome(base + ((uint64_t)t << 4), ptab), qs, ph_post);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) psi[base + ((uint64_t)t << 4) + r] = v[r];
+}
+
+// ---------------------------------------------------------------------------
+// high pass: link qubits [q0, q0+H) from registers, lanes on consecutive amplitudes
+// ---------------------------------------------------------------------------
+constexpr int kHighThreads = 256;
+
+template <typename T, int H>
+__global__ __launch_bounds__(kHighThreads) void k_high(const DevInst *__restrict__ insts, int q0,
+                                                       int step, int post, int n_plaq)
+{
+    using C = cplx_t<T>;
+    __shared__ uint32_t ptab[kPtabWords];
+    __shared__ C ph_post[kMaxPlaq + 1];
+    const DevInst in = insts[blockIdx.y];
+    if (in.step0 + step >= in.n_total) return;   // instance already finished (uniform per block)
+    C *__restrict__ psi = (C *)in.psi;
+    const RotParam<T> rp = ((const RotParam<T> *)in.rot)[in.step0 + step];
+    if (post >= 0) {
+        load_tables<T>(in, n_plaq, -1, post, ptab, nullptr, ph_post);
+        __syncthreads();
+    }
+    const uint64_t g = (uint64_t)blockIdx.x * kHighThreads + threadIdx.x;
+    const uint64_t lowmask = (1ull << q0) - 1;
+    const uint64_t base = (g & lowmask) | ((g >> q0) << (q0 + H));
+    C v[1 << H];
+#pragma unroll
+    for (int r = 0; r < (1 << H); ++r) v[r] = psi[base + ((uint64_t)r << q0)];
+    rot_regs<T, C, H>(v, rp.u, rp.v);
+    if (post >= 0) {
+        uint32_t qs[H];
+#pragma unroll
+        for (int k = 0; k < H; ++k) qs[k] = link_set(q0 + k, ptab);
+        apply_phase_regs<C, H>(v, syndrome(base, ptab), qs, ph_post);
+    }
+#pragma unroll
+    for (int r = 0; r < (1 << H); ++r) psi[base + ((uint64_t)r << q0)] = v[r];
+}
+
+// ---------------------------------------------------------------------------
+// standalone plaquette phase: 16 consecutive amplitudes per thread
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_phase(const DevInst *__restrict__ insts, int n,
+                                               int idx, int n_plaq)
+{
+    using C = cplx_t<T>;
+    __shared__ uint32_t ptab[kPtabWords];
+    __shared__ C ph[kMaxPlaq + 1];
+    const DevInst in = insts[blockIdx.y];
+    load_tables<T>(in, n_plaq, -1, idx, ptab, nullptr, ph);
+    __syncthreads();
+    C *__restrict__ psi = (C *)in.psi;
+    const uint64_t dim = 1ull << n;
+    const int nb = n < 4 ? n : 4;
+    uint32_t qs[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qs[k] = (k < nb) ? link_set(k, ptab) : 0u;
+    for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) << 4; base < dim;
+         base += ((uint64_t)gridDim.x * blockDim.x) << 4) {
+        const uint32_t P0 = syndrome(base, ptab);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (r < (1 << nb)) {
+                uint32_t P = P0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (r & (1 << k)) P ^= qs[k];
+                psi[base + r] = cmul(psi[base + r], ph[__popc(P)]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small states (n <= 12): the whole evolution of one instance in one workgroup,
+// state resident in LDS for every step of the call
+// ---------------------------------------------------------------------------
+constexpr int kSmallThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kSmallThreads) void k_small(const DevInst *__restrict__ insts, int n,
+                                                         int n_steps, int pre, int n_plaq)
+{
+    using C = cplx_t<T>;
+    __shared__ C a[1 << 12];
+    __shared__ uint32_t ptab[kPtabWords];
+    __shared__ uint8_t syn[1 << 12];
+    __shared__ C ph[kMaxPlaq + 1];
+    const DevInst in = insts[blockIdx.x];
+    C *__restrict__ psi = (C *)in.psi;
+    const int dim = 1 << n, t = threadIdx.x;
+    const int np1 = n_plaq + 1;
+    const C *phase = (const C *)in.phase;
+    const RotParam<T> *rot = (const RotParam<T> *)in.rot;
+    for (int i = t; i < kPtabWords; i += kSmallThreads) ptab[i] = in.ptab[i];
+    __syncthreads();
+    for (int b = t; b < dim; b += kSmallThreads) {
+        a[b] = psi[b];
+        syn[b] = (uint8_t)__popc(syndrome((uint64_t)b, ptab));
+    }
+    int k = in.ph0;
+    const int steps = min(n_steps, in.n_total - in.step0);
+    if (pre) {
+        for (int i = t; i < np1; i += kSmallThreads) ph[i] = phase[(size_t)k * np1 + i];
+        __syncthreads();
+        for (int b = t; b < dim; b += kSmallThreads) a[b] = cmul(a[b], ph[syn[b]]);
+        ++k;
+    }
+    __syncthreads();
+    for (int j = 0; j < steps; ++j, ++k) {
+        const RotParam<T> rp = rot[in.step0 + j];
+        for (int q = 0; q < n; ++q) {
+            const int lo = (1 << q) - 1;
+            for (int p = t; p < (dim >> 1); p += kSmallThreads) {
+                const int i0 = ((p & ~lo) << 1) | (p & lo);
+                rot_pair<T, C>(a[i0], a[i0 | (1 << q)], rp.u, rp.v);
+            }
+            __syncthreads();
+        }
+        for (int i = t; i < np1; i += kSmallThreads) ph[i] = phase[(size_t)k * np1 + i];
+        __syncthreads();
+        for (int b = t; b < dim; b += kSmallThreads) a[b] = cmul(a[b], ph[syn[b]]);
+        __syncthreads();
+    }
+    for (int b = t; b < dim; b += kSmallThreads) psi[b] = a[b];
+}
+
+// ---------------------------------------------------------------------------
+// state preparation
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_init(cplx_t<T> *psi, int n, int init, uint64_t basis, T amp,
+                       const uint32_t *__restrict__ ptab)
+{
+    const uint64_t dim = 1ull << n;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < dim;
+         b += (uint64_t)gridDim.x * blockDim.x) {
+        cplx_t<T> v;
+        v.y = 0;
+        if (init == LGT_INIT_PLUS) v.x = amp;
+        else if (init == LGT_INIT_BASIS) v.x = (b == basis) ? T(1) : T(0);
+        else v.x = syndrome(b, ptab) == 0u ? amp : T(0);
+        psi[b] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// circuit-form gates, one full-state pass each (eq. (ara) and the R_x layer)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_gate_rx(cplx_t<T> *psi, int n, int q, T c, T s)
+{
+    // R_x(phi) = exp(-i sigma^x phi/2): (a0, a1) <- (c a0 - i s a1, -i s a0 + c a1)
+    const uint64_t half = 1ull << (n - 1), lo = (1ull << q) - 1;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < half;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i0 = ((p & ~lo) << 1) | (p & lo), i1 = i0 | (lo + 1);
+        cplx_t<T> a0 = psi[i0], a1 = psi[i1], b0, b1;
+        b0.x = c * a0.x + s * a1.y;
+        b0.y = c * a0.y - s * a1.x;
+        b1.x = c * a1.x + s * a0.y;
+        b1.y = c * a1.y - s * a0.x;
+        psi[i0] = b0;
+        psi[i1] = b1;
+    }
+}
+
+template <typename T>
+__global__ void k_gate_rz(cplx_t<T> *psi, int n, int q, cplx_t<T> e0, cplx_t<T> e1)
+{
+    const uint64_t dim = 1ull << n;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < dim;
+         b += (uint64_t)gridDim.x * blockDim.x)
+        psi[b] = cmul(psi[b], ((b >> q) & 1) ? e1 : e0);
+}
+
+template <typename T>
+__global__ void k_gate_cnot(cplx_t<T> *psi, int n, int c, int t)
+{
+    // swap the pair (b, b ^ 2^t) for every b with control bit set and target bit clear
+    const int lo_b = c < t ? c : t, hi_b = c < t ? t : c;
+    const uint64_t quarter = 1ull << (n - 2);
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < quarter;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t i = p;
+        i = ((i >> lo_b) << (lo_b + 1)) | (i & ((1ull << lo_b) - 1));
+        i = ((i >> hi_b) << (hi_b + 1)) | (i & ((1ull << hi_b) - 1));
+        i |= 1ull << c;
+        const uint64_t j = i | (1ull << t);
+        cplx_t<T> x = psi[i];
+        psi[i] = psi[j];
+        psi[j] = x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions (Sec. 2.4: sums over all basis states)
+// ---------------------------------------------------------------------------
+constexpr int kRedThreads = 256;
+constexpr int kRedMasks = 32;     // masks per diagonal launch
+constexpr int kFlipMasks = 8;     // masks per off-diagonal launch
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// block-level sum of acc[M] into out[M] (deterministic order)
+template <int M>
+__device__ __forceinline__ void block_sum_store(double *acc, double *out)
+{
+    __shared__ double red[kRedThreads / 64][M];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double s = wave_sum(acc[m]);
+        if (lane == 0) red[w][m] = s;
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < M; m += kRedThreads) {
+        double s = 0;
+        for (int k = 0; k < kRedThreads / 64; ++k) s += red[k][m];
+        out[m] = s;
+    }
+}
+
+// acc[m] += |psi_b|^2 * (-1)^{popcount(b & mask_m)}
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_red_diag(const cplx_t<T> *__restrict__ psi, int n,
+                                                          const uint64_t *__restrict__ masks,
+                                                          int n_masks, double *partials)
+{
+    __shared__ uint64_t mk[kRedMasks];
+    if (threadIdx.x < kRedMasks) mk[threadIdx.x] = threadIdx.x < n_masks ? masks[threadIdx.x] : 0;
+    __syncthreads();
+    double acc[kRedMasks];
+#pragma unroll
+    for (int m = 0; m < kRedMasks; ++m) acc[m] = 0;
+    const uint64_t dim = 1ull << n;
+    for (uint64_t b = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; b < dim;
+         b += (uint64_t)gridDim.x * kRedThreads) {
+        const cplx_t<T> a = psi[b];
+        const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+#pragma unroll
+        for (int m = 0; m < kRedMasks; ++m) {
+            const uint64_t x = b & mk[m];
+            const int par = (__popc((uint32_t)x) + __popc((uint32_t)(x >> 32))) & 1;
+            acc[m] += par ? -p : p;
+        }
+    }
+    block_sum_store<kRedMasks>(acc, partials + (size_t)blockIdx.x * kRedMasks);
+}
+
+// acc[m] += Re conj(psi_b) psi_{b ^ mask_m}
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_red_flip(const cplx_t<T> *__restrict__ psi, int n,
+                                                          const uint64_t *__restrict__ masks,
+                                                          int n_masks, double *partials)
+{
+    __shared__ uint64_t mk[kFlipMasks];
+    if (threadIdx.x < kFlipMasks) mk[threadIdx.x] = threadIdx.x < n_masks ? masks[threadIdx.x] : 0;
+    __syncthreads();
+    double acc[kFlipMasks];
+#pragma unroll
+    for (int m = 0; m < kFlipMasks; ++m) acc[m] = 0;
+    const uint64_t dim = 1ull << n;
+    for (uint64_t b = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; b < dim;
+         b += (uint64_t)gridDim.x * kRedThreads) {
+        const cplx_t<T> a = psi[b];
+#pragma unroll
+        for (int m = 0; m < kFlipMasks; ++m) {
+            if (m < n_masks) {
+                const cplx_t<T> c = psi[b ^ mk[m]];
+                acc[m] += (double)a.x * (double)c.x + (double)a.y * (double)c.y;
+            }
+        }
+    }
+    block_sum_store<kFlipMasks>(acc, partials + (size_t)blockIdx.x * kFlipMasks);
+}
+
+// Z density of states: acc[m] += |psi_b|^2 for the m = popcount(P(b)) bin
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_red_dos(const cplx_t<T> *__restrict__ psi, int n,
+                                                         const uint32_t *__restrict__ ptab_g,
+                                                         int n_plaq, double *partials)
+{
+    __shared__ uint32_t ptab[kPtabWords];
+    for (int i = threadIdx.x; i < kPtabWords; i += kRedThreads) ptab[i] = ptab_g[i];
+    __syncthreads();
+    double acc[kMaxPlaq + 1];
+#pragma unroll
+    for (int m = 0; m <= kMaxPlaq; ++m) acc[m] = 0;
+    const uint64_t dim = 1ull << n;
+    for (uint64_t b = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; b < dim;
+         b += (uint64_t)gridDim.x * kRedThreads) {
+        const cplx_t<T> a = psi[b];
+        const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+        const int m = __popc(syndrome(b, ptab));
+#pragma unroll
+        for (int k = 0; k <= kMaxPlaq; ++k) acc[k] += (m == k) ? p : 0.0;
+    }
+    block_sum_store<kMaxPlaq + 1>(acc, partials + (size_t)blockIdx.x * (kMaxPlaq + 1));
+}
+
+// ---------------------------------------------------------------------------
+// sampling: FP64 block sums, prefix, inverse CDF per shot
+// ---------------------------------------------------------------------------
+constexpr int kSampleBlockBits = 10;   // amplitudes per block sum
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_sums(const cplx_t<T> *__restrict__ psi, int n,
+                                                    double *sums)
+{
+    // one block sum of 2^kSampleBlockBits amplitudes per 256-thread group, in a fixed order
+    __shared__ double red[256];
+    const int bb = n < kSampleBlockBits ? n : kSampleBlockBits;
+    const uint64_t base = (uint64_t)blockIdx.x << bb;
+    double s = 0;
+    for (int i = threadIdx.x; i < (1 << bb); i += 256) {
+        const cplx_t<T> a = psi[base + i];
+        s += (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+__device__ __forceinline__ double splitmix_uniform(uint64_t seed, uint64_t i)
+{
+    // SplitMix64 finaliser on the counter seed + (i+1) * golden gamma
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample(const cplx_t<T> *__restrict__ psi, int n,
+                                                const double *__restrict__ prefix, int n_blocks,
+                                                uint64_t n_shots, uint64_t seed, uint64_t *out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_shots) return;
+    const double total = prefix[n_blocks - 1];
+    const double target = splitmix_uniform(seed, i) * total;
+    // first block whose inclusive prefix exceeds the target
+    int lo = 0, hi = n_blocks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] > target) hi = mid; else lo = mid + 1;
+    }
+    const int bb = n < kSampleBlockBits ? n : kSampleBlockBits;
+    const uint64_t base = (uint64_t)lo << bb;
+    double acc = lo > 0 ? prefix[lo - 1] : 0.0;
+    uint64_t pick = base, last_nz = base;
+    bool found = false;
+    for (int k = 0; k < (1 << bb); ++k) {
+        const cplx_t<T> a = psi[base + k];
+        const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+        if (p > 0) last_nz = base + k;
+        acc += p;
+        if (acc > target) {
+            pick = base + k;
+            found = true;
+            break;
+        }
+    }
+    out[i] = found ? pick : last_nz;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+const char *kernel_family_name(int kf)
+{
+    static const char *names[KF_COUNT] = {"init", "pass_low", "pass_high", "phase", "small",
+                                          "gate_rx", "gate_rz", "gate_cnot", "reduce_diag",
+                                          "reduce_flip", "reduce_dos", "sample"};
+    return (kf >= 0 && kf < KF_COUNT) ? names[kf] : "?";
+}
+
+static unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap = 65536u)
+{
+    uint64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+hipError_t launch_init(int dtype, void *psi, int n, int init, uint64_t basis, double amp,
+                       const uint32_t *ptab_dev, hipStream_t st)
+{
+    const unsigned g = grid_for(1ull << n, 256, 16384);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(256), 0, st, (float2 *)psi, n, init,
+                           basis, (float)amp, ptab_dev);
+    else
+        hipLaunchKernelGGL(k_init<double>, dim3(g), dim3(256), 0, st, (double2 *)psi, n, init,
+                           basis, amp, ptab_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_low(int dtype, const DevInst *dev_inst, int n_inst, int n, int low_bits,
+                      int step, int pre, int post, int n_plaq, hipStream_t st)
+{
+    if (low_bits != kLowBits || n < kLowBits) return hipErrorInvalidValue;
+    dim3 grid((unsigned)(1ull << (n - kLowBits)), (unsigned)n_inst);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_low<float>, grid, dim3(kLowThreads), 0, st, dev_inst, step, pre,
+                           post, n_plaq);
+    else
+        hipLaunchKernelGGL(k_low<double>, grid, dim3(kLowThreads), 0, st, dev_inst, step, pre,
+                           post, n_plaq);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_high_t(const DevInst *dev_inst, int n_inst, int n, int q0, int h,
+                                int step, int post, int n_plaq, hipStream_t st)
+{
+    const uint64_t threads = 1ull << (n - h);
+    if (threads % kHighThreads) return hipErrorInvalidValue;
+    dim3 grid((unsigned)(threads / kHighThreads), (unsigned)n_inst);
+    switch (h) {
+    case 1: hipLaunchKernelGGL((k_high<T, 1>), grid, dim3(kHighThreads), 0, st, dev_inst, q0, step, post, n_plaq); break;
+    case 2: hipLaunchKernelGGL((k_high<T, 2>), grid, dim3(kHighThreads), 0, st, dev_inst, q0, step, post, n_plaq); break;
+    case 3: hipLaunchKernelGGL((k_high<T, 3>), grid, dim3(kHighThreads), 0, st, dev_inst, q0, step, post, n_plaq); break;
+    case 4: hipLaunchKernelGGL((k_high<T, 4>), grid, dim3(kHighThreads), 0, st, dev_inst, q0, step, post, n_plaq); break;
+    case 5: hipLaunchKernelGGL((k_high<T, 5>), grid, dim3(kHighThreads), 0, st, dev_inst, q0, step, post, n_plaq); break;
+    case 6: hipLaunchKernelGGL((k_high<T, 6>), grid, dim3(kHighThreads), 0, st, dev_inst, q0, step, post, n_plaq); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_high(int dtype, const DevInst *dev_inst, int n_inst, int n, int q0, int h,
+                       int step, int post, int n_plaq, hipStream_t st)
+{
+    // lanes of a wave must cover 64 consecutive amplitudes: q0 >= 6
+    if (q0 < 6 || q0 + h > n || h < 1) return hipErrorInvalidValue;
+    if (dtype == LGT_C64) return launch_high_t<float>(dev_inst, n_inst, n, q0, h, step, post, n_plaq, st);
+    if (h > 5) return hipErrorInvalidValue;
+    return launch_high_t<double>(dev_inst, n_inst, n, q0, h, step, post, n_plaq, st);
+}
+
+hipError_t launch_phase(int dtype, const DevInst *dev_inst, int n_inst, int n, int idx,
+                        int n_plaq, hipStream_t st)
+{
+    const uint64_t threads = (1ull << n) >> 4;
+    dim3 grid(grid_for(threads > 0 ? threads : 1, 256, 8192), (unsigned)n_inst);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_phase<float>, grid, dim3(256), 0, st, dev_inst, n, idx, n_plaq);
+    else
+        hipLaunchKernelGGL(k_phase<double>, grid, dim3(256), 0, st, dev_inst, n, idx, n_plaq);
+    return hipGetLastError();
+}
+
+bool small_supported(int dtype, int n) { (void)dtype; return n >= 1 && n <= 12; }
+
+hipError_t launch_small(int dtype, const DevInst *dev_inst, int n_inst, int n, int n_steps,
+                        int pre, int n_plaq, hipStream_t st)
+{
+    if (!small_supported(dtype, n)) return hipErrorInvalidValue;
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_small<float>, dim3(n_inst), dim3(kSmallThreads), 0, st, dev_inst, n,
+                           n_steps, pre, n_plaq);
+    else
+        hipLaunchKernelGGL(k_small<double>, dim3(n_inst), dim3(kSmallThreads), 0, st, dev_inst, n,
+                           n_steps, pre, n_plaq);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate_rx(int dtype, void *psi, int n, int q, double phi, hipStream_t st)
+{
+    const unsigned g = grid_for(1ull << (n - 1), 256, 16384);
+    const double c = std::cos(0.5 * phi), s = std::sin(0.5 * phi);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_gate_rx<float>, dim3(g), dim3(256), 0, st, (float2 *)psi, n, q,
+                           (float)c, (float)s);
+    else
+        hipLaunchKernelGGL(k_gate_rx<double>, dim3(g), dim3(256), 0, st, (double2 *)psi, n, q, c, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate_rz(int dtype, void *psi, int n, int q, double phi, hipStream_t st)
+{
+    // R_z(phi) = exp(-i sigma^z phi/2): |0> -> e^{-i phi/2}, |1> -> e^{+i phi/2}
+    const unsigned g = grid_for(1ull << n, 256, 16384);
+    const double c = std::cos(0.5 * phi), s = std::sin(0.5 * phi);
+    if (dtype == LGT_C64) {
+        float2 e0 = make_float2((float)c, (float)-s), e1 = make_float2((float)c, (float)s);
+        hipLaunchKernelGGL(k_gate_rz<float>, dim3(g), dim3(256), 0, st, (float2 *)psi, n, q, e0, e1);
+    } else {
+        double2 e0 = make_double2(c, -s), e1 = make_double2(c, s);
+        hipLaunchKernelGGL(k_gate_rz<double>, dim3(g), dim3(256), 0, st, (double2 *)psi, n, q, e0, e1);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gate_cnot(int dtype, void *psi, int n, int c, int t, hipStream_t st)
+{
+    if (n < 2 || c == t) return hipErrorInvalidValue;
+    const unsigned g = grid_for(1ull << (n - 2), 256, 16384);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_gate_cnot<float>, dim3(g), dim3(256), 0, st, (float2 *)psi, n, c, t);
+    else
+        hipLaunchKernelGGL(k_gate_cnot<double>, dim3(g), dim3(256), 0, st, (double2 *)psi, n, c, t);
+    return hipGetLastError();
+}
+
+int reduce_blocks(int n)
+{
+    const uint64_t work = (1ull << n) / (kRedThreads * 16ull);
+    return (int)grid_for(work > 0 ? work : 1, 1, 2048);
+}
+
+hipError_t launch_reduce_diag(int dtype, const void *psi, int n, const uint64_t *masks_dev,
+                              int n_masks, double *partials, hipStream_t st)
+{
+    if (n_masks < 1 || n_masks > kRedMasks) return hipErrorInvalidValue;
+    const int g = reduce_blocks(n);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_red_diag<float>, dim3(g), dim3(kRedThreads), 0, st,
+                           (const float2 *)psi, n, masks_dev, n_masks, partials);
+    else
+        hipLaunchKernelGGL(k_red_diag<double>, dim3(g), dim3(kRedThreads), 0, st,
+                           (const double2 *)psi, n, masks_dev, n_masks, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_flip(int dtype, const void *psi, int n, const uint64_t *masks_dev,
+                              int n_masks, double *partials, hipStream_t st)
+{
+    if (n_masks < 1 || n_masks > kFlipMasks) return hipErrorInvalidValue;
+    const int g = reduce_blocks(n);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_red_flip<float>, dim3(g), dim3(kRedThreads), 0, st,
+                           (const float2 *)psi, n, masks_dev, n_masks, partials);
+    else
+        hipLaunchKernelGGL(k_red_flip<double>, dim3(g), dim3(kRedThreads), 0, st,
+                           (const double2 *)psi, n, masks_dev, n_masks, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_dos(int dtype, const void *psi, int n, const uint32_t *ptab_dev,
+                             int n_plaq, double *partials, hipStream_t st)
+{
+    const int g = reduce_blocks(n);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_red_dos<float>, dim3(g), dim3(kRedThreads), 0, st,
+                           (const float2 *)psi, n, ptab_dev, n_plaq, partials);
+    else
+        hipLaunchKernelGGL(k_red_dos<double>, dim3(g), dim3(kRedThreads), 0, st,
+                           (const double2 *)psi, n, ptab_dev, n_plaq, partials);
+    return hipGetLastError();
+}
+
+int sample_block_bits(int n) { return n < kSampleBlockBits ? n : kSampleBlockBits; }
+
+hipError_t launch_sample(int dtype, const void *psi, int n, uint64_t n_shots, uint64_t seed,
+                         double *block_sums, double *block_prefix, uint64_t *out_dev,
+                         hipStream_t st)
+{
+    const int nb = 1 << (n - sample_block_bits(n));
+    hipError_t e;
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_block_sums<float>, dim3(nb), dim3(256), 0, st, (const float2 *)psi,
+                           n, block_sums);
+    else
+        hipLaunchKernelGGL(k_block_sums<double>, dim3(nb), dim3(256), 0, st,
+                           (const double2 *)psi, n, block_sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // inclusive prefix on the host in FP64, ascending block order
+    std::vector<double> h(nb);
+    if ((e = hipMemcpyAsync(h.data(), block_sums, sizeof(double) * nb, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    double acc = 0;
+    for (int i = 0; i < nb; ++i) {
+        acc += h[i];
+        h[i] = acc;
+    }
+    if ((e = hipMemcpyAsync(block_prefix, h.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    const unsigned g = (unsigned)((n_shots + 255) / 256);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_sample<float>, dim3(g), dim3(256), 0, st, (const float2 *)psi, n,
+                           block_prefix, nb, n_shots, seed, out_dev);
+    else
+        hipLaunchKernelGGL(k_sample<double>, dim3(g), dim3(256), 0, st, (const double2 *)psi, n,
+                           block_prefix, nb, n_shots, seed, out_dev);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+}  // namespace lgt

@@ -1,0 +1,151 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lgt.h"
+
+namespace lgt {
+
+constexpr int kMaxLinks = 34;     // 2^34 complex64 = 128 GiB: fits one 288 GB GPU
+constexpr int kMaxPlaq = 32;      // syndrome of all plaquettes fits a 32-bit word
+constexpr int kParityBytes = 5;   // byte tables cover 40 index bits
+
+// Periodic lattice (Sec. 2.1).  Sites numbered x-fastest; link l(s,mu) = d s + d-1-mu.
+struct Lattice {
+    int d = 0;
+    int L[3] = {1, 1, 1};
+    int n_sites = 0, n_links = 0, n_plaq = 0;
+    std::vector<int32_t> plaq_links;    // n_plaq * 4
+    std::vector<uint64_t> plaq_mask;    // n_plaq
+    std::vector<uint64_t> star_mask;    // n_sites
+    std::vector<uint32_t> link_plaqs;   // n_links: plaquettes touching each link
+    std::vector<int> fwd, bwd;          // neighbour tables [s * d + mu]
+
+    int link(int s, int mu) const { return d * s + (d - 1 - mu); }
+};
+
+// returns an empty string on success, else the reason
+std::string build_lattice(int d, const int *L, Lattice &out);
+uint64_t region_mask(const Lattice &lat, int site, int mu, int nu, int a, int b);
+uint64_t line_mask(const Lattice &lat, int site, int mu);
+
+// Plaquette syndrome tables: P(b) = XOR_k tab[k][(b >> 8k) & 255], bit p of P(b)
+// is the parity of plaquette p on basis state b.  P is linear over GF(2).
+void build_parity_tables(const Lattice &lat, uint32_t tab[kParityBytes][256]);
+
+// ---------------------------------------------------------------------------
+// Per-step device tables (Sec. 2.2 schedule, computed in FP64 on the host)
+// ---------------------------------------------------------------------------
+// The link layer prod_l exp(i a sigma^x_l) factors as scale * prod_l (u + i v sigma^x_l)
+// with (u, v) = (1, tan a) when |tan a| <= 1 and (cot a, 1) otherwise; each pair
+// update is then two FMAs per real component.  The scale (cos a)^N or (sin a)^N
+// is folded into the plaquette phase table applied right after the layer.
+template <typename T>
+struct RotParam {
+    T u, v;
+};
+
+template <typename T>
+struct Cplx {
+    T re, im;
+};
+
+struct StepTables {
+    int n_steps = 0;          // link layers in the call
+    int n_phase = 0;          // phase applications (n_steps, or n_steps+1 if symmetric)
+    int pre_phase = 0;        // 1: phase[0] is applied before the first link layer
+    std::vector<double> rot_u, rot_v;          // [n_steps]
+    std::vector<double> ph_re, ph_im;          // [n_phase * (n_plaq+1)]
+};
+
+// cx/cz: per-step coefficients of the steps in the call, dt the substep length.
+void build_step_tables(int n_links, int n_plaq, double dt, const double *cx, const double *cz,
+                       int n_steps, int order, StepTables &out);
+
+// Round to complex64 tables; chooses each float (u, v) and phase entry among
+// nearby floats so the norm of one full step stays 1 to FP32 rounding.
+void round_tables_f32(const StepTables &in, int n_links, int n_plaq,
+                      std::vector<RotParam<float>> &rot, std::vector<Cplx<float>> &ph);
+void round_tables_f64(const StepTables &in, int n_plaq,
+                      std::vector<RotParam<double>> &rot, std::vector<Cplx<double>> &ph);
+
+// Expand an lgt_schedule into per-step coefficients for steps [first, first+count).
+std::string schedule_coeffs(const lgt_schedule *s, int64_t first, int64_t count, double &dt,
+                            std::vector<double> &cx, std::vector<double> &cz);
+
+// ---------------------------------------------------------------------------
+// Device-side instance description used by every pass kernel.  Batched
+// launches read instance blockIdx.y from an array of these.
+// ---------------------------------------------------------------------------
+struct DevInst {
+    void *psi;                 // amplitudes
+    const void *rot;           // RotParam<T>[n_total]
+    const void *phase;         // Cplx<T>[n_phase][n_plaq+1]
+    const uint32_t *ptab;      // [kParityBytes][256] syndrome byte tables
+    int step0;                 // link layer step0 + step of a launch uses rot[step0 + step]
+    int ph0;                   // phase index idx of a launch reads phase[ph0 + idx]
+    int n_total;               // steps in rot; launches past the end leave the instance alone
+    int pad;
+};
+
+// kernel launch plan for one link layer of an N-link state
+struct PassPlan {
+    int n_passes = 0;
+    int low_bits = 0;          // first pass: contiguous tile of 2^low_bits amplitudes
+    int hi_q0[8] = {0};        // further passes: qubits [q0, q0+h) from registers
+    int hi_h[8] = {0};
+};
+PassPlan plan_passes(int n_links, int dtype);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (kernels.hip).  All return hipSuccess or the HIP error.
+// ---------------------------------------------------------------------------
+enum KernelFamily {
+    KF_INIT = 0, KF_LOW, KF_HIGH, KF_PHASE, KF_SMALL, KF_GATE_RX, KF_GATE_RZ, KF_GATE_CNOT,
+    KF_RED_DIAG, KF_RED_FLIP, KF_RED_DOS, KF_SAMPLE, KF_COUNT
+};
+const char *kernel_family_name(int kf);
+
+hipError_t launch_init(int dtype, void *psi, int n, int init, uint64_t basis, double amp,
+                       const uint32_t *ptab_dev, hipStream_t st);
+// one link layer pass over n_inst instances (pointers in dev_inst, device memory)
+hipError_t launch_low(int dtype, const DevInst *dev_inst, int n_inst, int n, int low_bits,
+                      int step, int pre_phase_idx, int post_phase_idx, int n_plaq,
+                      hipStream_t st);
+hipError_t launch_high(int dtype, const DevInst *dev_inst, int n_inst, int n, int q0, int h,
+                       int step, int post_phase_idx, int n_plaq, hipStream_t st);
+hipError_t launch_phase(int dtype, const DevInst *dev_inst, int n_inst, int n, int phase_idx,
+                        int n_plaq, hipStream_t st);
+// whole evolution of small states (n <= 12) held in LDS, one workgroup per instance
+hipError_t launch_small(int dtype, const DevInst *dev_inst, int n_inst, int n, int n_steps,
+                        int pre_phase, int n_plaq, hipStream_t st);
+// enqueue `count` fused substeps for n_inst instances (api.cpp); pre_first: phase index
+// applied before the first link layer or -1; the phase after layer j is post_off + j
+hipError_t enqueue_fused_steps(int dtype, int n_links, int n_plaq, const DevInst *dev_inst,
+                               int n_inst, int count, int pre_first, int post_off,
+                               hipStream_t st, void *prof_ctx);
+bool small_supported(int dtype, int n);
+// circuit-form gates
+hipError_t launch_gate_rx(int dtype, void *psi, int n, int q, double phi, hipStream_t st);
+hipError_t launch_gate_rz(int dtype, void *psi, int n, int q, double phi, hipStream_t st);
+hipError_t launch_gate_cnot(int dtype, void *psi, int n, int c, int t, hipStream_t st);
+// reductions: partial sums per block, FP64
+int reduce_blocks(int n);
+hipError_t launch_reduce_diag(int dtype, const void *psi, int n, const uint64_t *masks_dev,
+                              int n_masks, double *partials, hipStream_t st);
+hipError_t launch_reduce_flip(int dtype, const void *psi, int n, const uint64_t *masks_dev,
+                              int n_masks, double *partials, hipStream_t st);
+hipError_t launch_reduce_dos(int dtype, const void *psi, int n, const uint32_t *ptab_dev,
+                             int n_plaq, double *partials, hipStream_t st);
+// sampling: block sums -> prefix -> inverse CDF
+int sample_block_bits(int n);
+hipError_t launch_sample(int dtype, const void *psi, int n, uint64_t n_shots, uint64_t seed,
+                         double *block_sums, double *block_prefix, uint64_t *out_dev,
+                         hipStream_t st);
+
+}  // namespace lgt

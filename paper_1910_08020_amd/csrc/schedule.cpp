@@ -1,0 +1,176 @@
+// Host FP64 schedule and per-step tables (Sec. 2.2 of arXiv:1910.08020).
+//
+// Step j of a run of n substeps of length dt = T/n uses the coupling at the
+// substep's right end, f_j = (j+1)/n, as in g_{k,m} = (k-1) g_s + m delta.
+// First order (eq. (a)) applies the link layer, then the plaquette phase.
+// The symmetric order (eq. (s)) brackets the link layer with two half phases;
+// inside one call the half phases of neighbouring substeps are merged into a
+// single phase table, as in the rewritten product that follows eq. (s).
+#include <cmath>
+#include <limits>
+
+#include "lgt_internal.hpp"
+
+namespace lgt {
+
+std::string schedule_coeffs(const lgt_schedule *s, int64_t first, int64_t count, double &dt,
+                            std::vector<double> &cx, std::vector<double> &cz)
+{
+    if (!s) return "null schedule";
+    if (s->n_steps < 1) return "schedule needs n_steps >= 1";
+    if (!std::isfinite(s->T) || s->T == 0.0) return "schedule T must be finite and nonzero";
+    if (first < 0 || count < 0 || first + count > s->n_steps)
+        return "step range outside [0, n_steps)";
+    if (count > (int64_t)1 << 30) return "too many steps in one call";
+    if (s->s_rule != 0 && s->s_rule != 1) return "s_rule must be 0 or 1";
+    dt = s->T / (double)s->n_steps;
+    cx.resize(count);
+    cz.resize(count);
+    const double n = (double)s->n_steps;
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t j = first + i;
+        const double f = s->s_rule == 0 ? (double)(j + 1) / n : ((double)j + 0.5) / n;
+        switch (s->ramp) {
+        case LGT_RAMP_PLAQ:
+            cx[i] = s->h_x;
+            cz[i] = f * s->h_p;
+            break;
+        case LGT_RAMP_COUPLING:
+            cx[i] = s->g0 + (s->g1 - s->g0) * f;
+            cz[i] = 1.0;
+            break;
+        case LGT_RAMP_EXPLICIT:
+            if (!s->cx || !s->cz) return "explicit schedule needs cx and cz arrays";
+            cx[i] = s->cx[j];
+            cz[i] = s->cz[j];
+            break;
+        default:
+            return "unknown ramp";
+        }
+        if (!std::isfinite(cx[i]) || !std::isfinite(cz[i])) return "non-finite coefficient";
+    }
+    return "";
+}
+
+void build_step_tables(int n_links, int n_plaq, double dt, const double *cx, const double *cz,
+                       int n_steps, int order, StepTables &out)
+{
+    out.n_steps = n_steps;
+    out.pre_phase = (order == LGT_ORDER_SYMMETRIC) ? 1 : 0;
+    out.n_phase = n_steps + out.pre_phase;
+    out.rot_u.resize(n_steps);
+    out.rot_v.resize(n_steps);
+    std::vector<double> scale(n_steps);
+    for (int j = 0; j < n_steps; ++j) {
+        // exp(+i a sigma^x) = cos a + i sin a sigma^x, a = dt cx_j  (R_x(-2 a))
+        const double a = dt * cx[j];
+        const double c = std::cos(a), s = std::sin(a);
+        if (std::fabs(c) >= std::fabs(s)) {
+            out.rot_u[j] = 1.0;
+            out.rot_v[j] = s / c;
+            scale[j] = std::pow(c, n_links);
+        } else {
+            out.rot_u[j] = c / s;
+            out.rot_v[j] = 1.0;
+            scale[j] = std::pow(s, n_links);
+        }
+    }
+    const int np1 = n_plaq + 1;
+    out.ph_re.assign((size_t)out.n_phase * np1, 0.0);
+    out.ph_im.assign((size_t)out.n_phase * np1, 0.0);
+    auto fill = [&](int k, double theta, double sc) {
+        // exp(-i t Hz) with Hz = -cz sum U_p: phase e^{i theta (n_plaq - 2m)} for m odd plaquettes
+        for (int m = 0; m <= n_plaq; ++m) {
+            const double ang = theta * (double)(n_plaq - 2 * m);
+            out.ph_re[(size_t)k * np1 + m] = sc * std::cos(ang);
+            out.ph_im[(size_t)k * np1 + m] = sc * std::sin(ang);
+        }
+    };
+    if (order == LGT_ORDER_TROTTER) {
+        for (int j = 0; j < n_steps; ++j) fill(j, dt * cz[j], scale[j]);
+    } else {
+        if (n_steps > 0) fill(0, 0.5 * dt * cz[0], 1.0);
+        for (int j = 0; j < n_steps; ++j) {
+            const double th = (j + 1 < n_steps) ? 0.5 * dt * (cz[j] + cz[j + 1]) : 0.5 * dt * cz[j];
+            fill(j + 1, th, scale[j]);
+        }
+    }
+}
+
+// Nearest float, then the +-2 ulp neighbourhood searched for the pair whose
+// squared magnitude is closest to the target (ties: closest to the value).
+static void round_pair_norm(double x, double y, double target2, float &fx, float &fy)
+{
+    const float x0 = (float)x, y0 = (float)y;
+    float cx[5], cy[5];
+    cx[2] = x0;
+    cy[2] = y0;
+    cx[1] = std::nextafter(x0, -INFINITY); cx[0] = std::nextafter(cx[1], -INFINITY);
+    cx[3] = std::nextafter(x0, INFINITY);  cx[4] = std::nextafter(cx[3], INFINITY);
+    cy[1] = std::nextafter(y0, -INFINITY); cy[0] = std::nextafter(cy[1], -INFINITY);
+    cy[3] = std::nextafter(y0, INFINITY);  cy[4] = std::nextafter(cy[3], INFINITY);
+    long double best = std::numeric_limits<long double>::infinity(), bestd = best;
+    fx = x0;
+    fy = y0;
+    for (int i = 0; i < 5; ++i)
+        for (int k = 0; k < 5; ++k) {
+            long double a = cx[i], b = cy[k];
+            long double e = std::fabs(a * a + b * b - (long double)target2);
+            long double dd = (a - x) * (a - x) + (b - y) * (b - y);
+            if (e < best || (e == best && dd < bestd)) {
+                best = e;
+                bestd = dd;
+                fx = cx[i];
+                fy = cy[k];
+            }
+        }
+}
+
+void round_tables_f32(const StepTables &in, int n_links, int n_plaq,
+                      std::vector<RotParam<float>> &rot, std::vector<Cplx<float>> &ph)
+{
+    const int np1 = n_plaq + 1;
+    rot.resize(in.n_steps);
+    std::vector<long double> gain(in.n_steps);  // norm gain of the float link layer
+    for (int j = 0; j < in.n_steps; ++j) {
+        rot[j].u = (float)in.rot_u[j];
+        rot[j].v = (float)in.rot_v[j];
+        long double g = (long double)rot[j].u * rot[j].u + (long double)rot[j].v * rot[j].v;
+        gain[j] = std::pow(g, (long double)n_links);
+    }
+    ph.resize((size_t)in.n_phase * np1);
+    for (int k = 0; k < in.n_phase; ++k) {
+        // the phase after link layer j undoes that layer's gain exactly
+        const int j = k - in.pre_phase;
+        const long double target2 = (j >= 0) ? 1.0L / gain[j] : 1.0L;
+        // sign of the folded cos^N / sin^N factor, from the FP64 table
+        double mag = 0;
+        for (int m = 0; m < np1; ++m)
+            mag = std::max(mag, std::hypot(in.ph_re[(size_t)k * np1 + m],
+                                           in.ph_im[(size_t)k * np1 + m]));
+        const double rescale = (mag > 0) ? std::sqrt((double)target2) / mag : 1.0;
+        for (int m = 0; m < np1; ++m) {
+            const size_t i = (size_t)k * np1 + m;
+            round_pair_norm(in.ph_re[i] * rescale, in.ph_im[i] * rescale, (double)target2,
+                            ph[i].re, ph[i].im);
+        }
+    }
+}
+
+void round_tables_f64(const StepTables &in, int n_plaq, std::vector<RotParam<double>> &rot,
+                      std::vector<Cplx<double>> &ph)
+{
+    const int np1 = n_plaq + 1;
+    rot.resize(in.n_steps);
+    for (int j = 0; j < in.n_steps; ++j) {
+        rot[j].u = in.rot_u[j];
+        rot[j].v = in.rot_v[j];
+    }
+    ph.resize((size_t)in.n_phase * np1);
+    for (size_t i = 0; i < ph.size(); ++i) {
+        ph[i].re = in.ph_re[i];
+        ph[i].im = in.ph_im[i];
+    }
+}
+
+}  // namespace lgt

@@ -1,0 +1,519 @@
+// Continuous-batching server for adiabatic runs of mixed lattice sizes.
+//
+// Requests are admitted first-in first-out while their state and tables fit
+// the HBM budget and a slot is free.  A worker thread advances every admitted
+// run by up to chunk_steps substeps per round; runs of the same lattice and
+// precision share one launch per pass (each instance at its own step offset),
+// so a run that arrives while others are on the GPU joins at the next round.
+// A finished run is read out on the GPU (energy, plaquettes, Gauss law) and its
+// memory goes back to the budget.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "lgt_internal.hpp"
+
+using namespace lgt;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_between(Clock::time_point a, Clock::time_point b)
+{
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+struct Shape {
+    int d, L[3], dtype;
+    bool operator<(const Shape &o) const
+    {
+        if (d != o.d) return d < o.d;
+        if (dtype != o.dtype) return dtype < o.dtype;
+        return std::memcmp(L, o.L, sizeof L) < 0;
+    }
+};
+
+struct ShapeRes {
+    Lattice lat;
+    uint32_t *ptab_dev = nullptr;
+    size_t state_bytes = 0;
+};
+
+struct Run {
+    uint64_t ticket = 0;
+    Shape shape{};
+    const ShapeRes *sr = nullptr;  // stable pointer into the server's shape map
+    bool admitted = false;         // footprint counted against the budget
+    lgt_schedule sched{};
+    std::vector<double> cx_copy, cz_copy;
+    int order = LGT_ORDER_TROTTER;
+    size_t footprint = 0;
+    Clock::time_point t_submit, t_admit;
+    // resident state (valid while admitted)
+    void *psi = nullptr;
+    void *tables = nullptr;        // rot | phase
+    size_t rot_bytes = 0;
+    int n_total = 0, pre = 0, step = 0;
+    double cx_last = 0, cz_last = 0;
+};
+
+}  // namespace
+
+struct lgt_server {
+    size_t budget = 0, used = 0;
+    int max_slots = 0, chunk = 0, device = 0;
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Run *> pending;
+    std::vector<Run *> active;
+    std::map<uint64_t, lgt_result> results;
+    std::map<Shape, ShapeRes> shapes;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+    // device scratch owned by the worker
+    DevInst *inst_dev = nullptr;
+    size_t inst_cap = 0;
+    double *partials = nullptr;
+    std::vector<double> partials_host;
+    uint64_t *masks_dev = nullptr;
+    void *stage = nullptr;
+    size_t stage_cap = 0;
+};
+
+namespace {
+
+constexpr int kParts = 2048 * (kMaxPlaq + 1);
+
+size_t elem_bytes(int dtype) { return dtype == LGT_C64 ? 8 : 16; }
+
+hipError_t stage_to_device(lgt_server *s, void *dst, const void *src, size_t n)
+{
+    if (s->stage_cap < n) {
+        if (s->stage) (void)hipHostFree(s->stage);
+        s->stage = nullptr;
+        s->stage_cap = 0;
+        hipError_t e = hipHostMalloc(&s->stage, n, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        s->stage_cap = n;
+    }
+    std::memcpy(s->stage, src, n);
+    hipError_t e = hipMemcpyAsync(dst, s->stage, n, hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s->stream);   // staging buffer reused right after
+}
+
+// sum of per-block partials over the masks of one reduction launch
+hipError_t reduce(lgt_server *s, int dtype, const void *psi, int n, bool flip,
+                  const uint64_t *masks, int n_masks, std::vector<long double> &out)
+{
+    const int chunk = flip ? 8 : 32;
+    const int g = reduce_blocks(n);
+    out.assign(n_masks, 0.0L);
+    for (int k0 = 0; k0 < n_masks; k0 += chunk) {
+        const int m = std::min(chunk, n_masks - k0);
+        hipError_t e = hipMemcpyAsync(s->masks_dev, masks + k0, sizeof(uint64_t) * m,
+                                      hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return e;
+        e = flip ? launch_reduce_flip(dtype, psi, n, s->masks_dev, m, s->partials, s->stream)
+                 : launch_reduce_diag(dtype, psi, n, s->masks_dev, m, s->partials, s->stream);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(s->partials_host.data(), s->partials, sizeof(double) * g * chunk,
+                           hipMemcpyDeviceToHost, s->stream);
+        if (e != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return e;
+        for (int i = 0; i < m; ++i) {
+            long double acc = 0;
+            for (int b = 0; b < g; ++b) acc += s->partials_host[(size_t)b * chunk + i];
+            out[k0 + i] = acc;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t readout(lgt_server *s, Run *r, lgt_result &res)
+{
+    const Lattice &lat = r->sr->lat;
+    const int n = lat.n_links;
+    std::vector<uint64_t> diag(1, 0ull);
+    diag.insert(diag.end(), lat.plaq_mask.begin(), lat.plaq_mask.end());
+    std::vector<uint64_t> flip;
+    for (int q = 0; q < n; ++q) flip.push_back(1ull << q);
+    flip.insert(flip.end(), lat.star_mask.begin(), lat.star_mask.end());
+    std::vector<long double> vd, vf;
+    hipError_t e = reduce(s, r->shape.dtype, r->psi, n, false, diag.data(), (int)diag.size(), vd);
+    if (e != hipSuccess) return e;
+    e = reduce(s, r->shape.dtype, r->psi, n, true, flip.data(), (int)flip.size(), vf);
+    if (e != hipSuccess) return e;
+    const long double nrm = vd[0];
+    long double plaq = 0, sx = 0, gv = 0;
+    for (int p = 0; p < lat.n_plaq; ++p) plaq += vd[1 + p];
+    for (int q = 0; q < n; ++q) sx += vf[q];
+    for (int i = 0; i < lat.n_sites; ++i)
+        gv = std::max(gv, std::fabs(1.0L - vf[n + i] / nrm));
+    res.norm = (double)nrm;
+    res.plaq_mean = (double)(plaq / nrm / lat.n_plaq);
+    res.energy = (double)((-(long double)r->cx_last * sx - (long double)r->cz_last * plaq) / nrm);
+    res.gauss_violation = (double)gv;
+    return hipSuccess;
+}
+
+void finish(lgt_server *s, Run *r, lgt_status st, const lgt_result *res_in)
+{
+    lgt_result res{};
+    if (res_in) res = *res_in;
+    res.done = 1;
+    res.status = st;
+    const auto now = Clock::now();
+    res.latency_ms = ms_between(r->t_submit, now);
+    res.queue_ms = (r->t_admit.time_since_epoch().count() ? ms_between(r->t_submit, r->t_admit)
+                                                           : res.latency_ms);
+    if (r->psi) (void)hipFreeAsync(r->psi, s->stream);
+    if (r->tables) (void)hipFreeAsync(r->tables, s->stream);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (r->admitted) s->used -= r->footprint;
+        s->results[r->ticket] = res;
+    }
+    s->cv_done.notify_all();
+    delete r;
+}
+
+// allocate, upload tables and prepare |+>^N (plus the leading half phase)
+lgt_status admit(lgt_server *s, Run *r)
+{
+    const ShapeRes &sr = *r->sr;
+    const Lattice &lat = sr.lat;
+    const int n = lat.n_links, dtype = r->shape.dtype;
+    double dt;
+    std::vector<double> cx, cz;
+    if (!schedule_coeffs(&r->sched, 0, r->sched.n_steps, dt, cx, cz).empty()) return LGT_E_INVALID;
+    r->cx_last = cx.back();
+    r->cz_last = cz.back();
+    StepTables st;
+    build_step_tables(n, lat.n_plaq, dt, cx.data(), cz.data(), (int)cx.size(), r->order, st);
+    std::vector<char> blob;
+    if (dtype == LGT_C64) {
+        std::vector<RotParam<float>> rot;
+        std::vector<Cplx<float>> ph;
+        round_tables_f32(st, n, lat.n_plaq, rot, ph);
+        r->rot_bytes = (rot.size() * sizeof(rot[0]) + 255) & ~(size_t)255;
+        blob.resize(r->rot_bytes + ph.size() * sizeof(ph[0]));
+        std::memcpy(blob.data(), rot.data(), rot.size() * sizeof(rot[0]));
+        std::memcpy(blob.data() + r->rot_bytes, ph.data(), ph.size() * sizeof(ph[0]));
+    } else {
+        std::vector<RotParam<double>> rot;
+        std::vector<Cplx<double>> ph;
+        round_tables_f64(st, lat.n_plaq, rot, ph);
+        r->rot_bytes = (rot.size() * sizeof(rot[0]) + 255) & ~(size_t)255;
+        blob.resize(r->rot_bytes + ph.size() * sizeof(ph[0]));
+        std::memcpy(blob.data(), rot.data(), rot.size() * sizeof(rot[0]));
+        std::memcpy(blob.data() + r->rot_bytes, ph.data(), ph.size() * sizeof(ph[0]));
+    }
+    r->n_total = st.n_steps;
+    r->pre = st.pre_phase;
+    r->step = 0;
+    if (hipMallocAsync(&r->psi, sr.state_bytes, s->stream) != hipSuccess) return LGT_E_OOM;
+    if (hipMallocAsync(&r->tables, blob.size() + 256, s->stream) != hipSuccess) return LGT_E_OOM;
+    if (stage_to_device(s, r->tables, blob.data(), blob.size()) != hipSuccess) return LGT_E_DEVICE;
+    const double amp = std::ldexp(1.0, -n / 2) * ((n & 1) ? std::sqrt(0.5) : 1.0);
+    if (launch_init(dtype, r->psi, n, LGT_INIT_PLUS, 0, amp, sr.ptab_dev, s->stream) != hipSuccess)
+        return LGT_E_DEVICE;
+    if (r->pre) {
+        DevInst di{};
+        di.psi = r->psi;
+        di.rot = r->tables;
+        di.phase = (char *)r->tables + r->rot_bytes;
+        di.ptab = sr.ptab_dev;
+        di.n_total = r->n_total;
+        if (stage_to_device(s, s->inst_dev, &di, sizeof di) != hipSuccess) return LGT_E_DEVICE;
+        if (launch_phase(dtype, s->inst_dev, 1, n, 0, lat.n_plaq, s->stream) != hipSuccess)
+            return LGT_E_DEVICE;
+        if (hipStreamSynchronize(s->stream) != hipSuccess) return LGT_E_DEVICE;
+    }
+    r->t_admit = Clock::now();
+    return LGT_OK;
+}
+
+void worker_loop(lgt_server *s)
+{
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        std::vector<Run *> newly;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
+            if (s->stop && s->active.empty()) {
+                // cancel what was never admitted
+                while (!s->pending.empty()) {
+                    Run *r = s->pending.front();
+                    s->pending.pop_front();
+                    lgt_result res{};
+                    res.done = 1;
+                    res.status = LGT_E_STATE;
+                    res.latency_ms = ms_between(r->t_submit, Clock::now());
+                    s->results[r->ticket] = res;
+                    delete r;
+                }
+                s->cv_done.notify_all();
+                return;
+            }
+            // FIFO admission by slot and HBM footprint
+            while (!s->stop && !s->pending.empty() &&
+                   (int)(s->active.size() + newly.size()) < s->max_slots &&
+                   s->used + s->pending.front()->footprint <= s->budget) {
+                Run *r = s->pending.front();
+                s->pending.pop_front();
+                s->used += r->footprint;
+                r->admitted = true;
+                newly.push_back(r);
+            }
+        }
+        for (Run *r : newly) {
+            lgt_status st = admit(s, r);
+            if (st != LGT_OK) {
+                finish(s, r, st, nullptr);
+                continue;
+            }
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->active.push_back(r);
+        }
+        std::vector<Run *> act;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            act = s->active;
+        }
+        if (act.empty()) continue;
+        // one batched launch sequence per lattice shape
+        std::map<Shape, std::vector<Run *>> groups;
+        for (Run *r : act) groups[r->shape].push_back(r);
+        size_t need = 0;
+        for (auto &g : groups) need += ((g.second.size() * sizeof(DevInst)) + 255) & ~(size_t)255;
+        if (s->inst_cap < need) {
+            (void)hipStreamSynchronize(s->stream);
+            if (s->inst_dev) (void)hipFree(s->inst_dev);
+            s->inst_dev = nullptr;
+            s->inst_cap = 0;
+            if (hipMalloc((void **)&s->inst_dev, need * 2) != hipSuccess) {
+                for (Run *r : act) finish(s, r, LGT_E_OOM, nullptr);
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->active.clear();
+                continue;
+            }
+            s->inst_cap = need * 2;
+        }
+        std::vector<char> host(need);
+        size_t off = 0;
+        bool dev_fail = false;
+        std::vector<std::pair<size_t, std::pair<Shape, int>>> launches;
+        for (auto &g : groups) {
+            const ShapeRes &sr = *g.second[0]->sr;
+            DevInst *di = (DevInst *)(host.data() + off);
+            for (size_t i = 0; i < g.second.size(); ++i) {
+                Run *r = g.second[i];
+                di[i] = DevInst{};
+                di[i].psi = r->psi;
+                di[i].rot = r->tables;
+                di[i].phase = (char *)r->tables + r->rot_bytes;
+                di[i].ptab = sr.ptab_dev;
+                di[i].step0 = r->step;
+                di[i].ph0 = r->step + r->pre;
+                di[i].n_total = r->n_total;
+            }
+            launches.push_back({off, {g.first, (int)g.second.size()}});
+            off += ((g.second.size() * sizeof(DevInst)) + 255) & ~(size_t)255;
+        }
+        if (stage_to_device(s, s->inst_dev, host.data(), need) != hipSuccess) dev_fail = true;
+        for (auto &l : launches) {
+            if (dev_fail) break;
+            const ShapeRes &sr = *groups[l.second.first][0]->sr;
+            int steps = 0;
+            for (Run *r : groups[l.second.first]) steps = std::max(steps, r->n_total - r->step);
+            steps = std::min(steps, s->chunk);
+            if (enqueue_fused_steps(l.second.first.dtype, sr.lat.n_links, sr.lat.n_plaq,
+                                    (const DevInst *)((char *)s->inst_dev + l.first),
+                                    l.second.second, steps, -1, 0, s->stream, nullptr) != hipSuccess)
+                dev_fail = true;
+        }
+        if (!dev_fail && hipStreamSynchronize(s->stream) != hipSuccess) dev_fail = true;
+        std::vector<Run *> still;
+        for (Run *r : act) {
+            if (dev_fail) {
+                finish(s, r, LGT_E_DEVICE, nullptr);
+                continue;
+            }
+            r->step = std::min(r->n_total, r->step + s->chunk);
+            if (r->step >= r->n_total) {
+                lgt_result res{};
+                const bool ok = readout(s, r, res) == hipSuccess;
+                finish(s, r, ok ? LGT_OK : LGT_E_DEVICE, &res);
+            } else {
+                still.push_back(r);
+            }
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->active = still;
+    }
+}
+
+lgt_status fail_null(const char *) { return LGT_E_INVALID; }
+
+}  // namespace
+
+extern "C" {
+
+lgt_status lgt_server_create(size_t hbm_budget, int max_slots, int chunk_steps, lgt_server **out)
+{
+    if (!out || max_slots < 1 || max_slots > 65535 || chunk_steps < 1 || hbm_budget == 0)
+        return fail_null("bad server arguments");
+    *out = nullptr;
+    lgt_server *s = new lgt_server();
+    s->budget = hbm_budget;
+    s->max_slots = max_slots;
+    s->chunk = chunk_steps;
+    if (hipGetDevice(&s->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc((void **)&s->partials, sizeof(double) * kParts) != hipSuccess ||
+        hipMalloc((void **)&s->masks_dev, sizeof(uint64_t) * 64) != hipSuccess ||
+        hipMalloc((void **)&s->inst_dev, 4096) != hipSuccess) {
+        if (s->stream) (void)hipStreamDestroy(s->stream);
+        if (s->partials) (void)hipFree(s->partials);
+        if (s->masks_dev) (void)hipFree(s->masks_dev);
+        delete s;
+        return LGT_E_DEVICE;
+    }
+    s->inst_cap = 4096;
+    s->partials_host.resize(kParts);
+    s->worker = std::thread(worker_loop, s);
+    *out = s;
+    return LGT_OK;
+}
+
+lgt_status lgt_server_submit(lgt_server *s, const lgt_request *req, uint64_t *ticket)
+{
+    if (!s || !req || !ticket) return LGT_E_INVALID;
+    if (req->dtype != LGT_C64 && req->dtype != LGT_C128) return LGT_E_INVALID;
+    if (req->order != LGT_ORDER_TROTTER && req->order != LGT_ORDER_SYMMETRIC) return LGT_E_INVALID;
+    Shape sh{};
+    sh.d = req->d;
+    sh.dtype = req->dtype;
+    for (int i = 0; i < 3; ++i) sh.L[i] = (i < req->d) ? req->L[i] : 1;
+    Run *r = new Run();
+    r->shape = sh;
+    r->sched = req->sched;
+    r->order = req->order;
+    if (req->sched.ramp == LGT_RAMP_EXPLICIT) {
+        if (!req->sched.cx || !req->sched.cz || req->sched.n_steps < 1) {
+            delete r;
+            return LGT_E_INVALID;
+        }
+        r->cx_copy.assign(req->sched.cx, req->sched.cx + req->sched.n_steps);
+        r->cz_copy.assign(req->sched.cz, req->sched.cz + req->sched.n_steps);
+        r->sched.cx = r->cx_copy.data();
+        r->sched.cz = r->cz_copy.data();
+    }
+    double dt;
+    std::vector<double> cx, cz;
+    if (!schedule_coeffs(&r->sched, 0, r->sched.n_steps, dt, cx, cz).empty() ||
+        r->sched.n_steps > (1 << 24)) {
+        delete r;
+        return LGT_E_INVALID;
+    }
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->shapes.find(sh);
+    if (it == s->shapes.end()) {
+        ShapeRes sr;
+        std::string why = build_lattice(req->d, req->L, sr.lat);
+        if (!why.empty()) {
+            delete r;
+            return why.find("too many") != std::string::npos ? LGT_E_UNSUPPORTED : LGT_E_INVALID;
+        }
+        uint32_t tab[kParityBytes][256];
+        build_parity_tables(sr.lat, tab);
+        if (hipSetDevice(s->device) != hipSuccess || hipMalloc((void **)&sr.ptab_dev, sizeof tab) != hipSuccess ||
+            hipMemcpy(sr.ptab_dev, tab, sizeof tab, hipMemcpyHostToDevice) != hipSuccess) {
+            delete r;
+            return LGT_E_DEVICE;
+        }
+        sr.state_bytes = ((size_t)1 << sr.lat.n_links) * elem_bytes(sh.dtype);
+        it = s->shapes.emplace(sh, std::move(sr)).first;
+    }
+    const ShapeRes &sr = it->second;
+    r->sr = &it->second;
+    const size_t steps = (size_t)r->sched.n_steps;
+    r->footprint = sr.state_bytes + steps * 2 * 8 * (sh.dtype == LGT_C64 ? 1 : 2) +
+                   (steps + 1) * (sr.lat.n_plaq + 1) * elem_bytes(sh.dtype) + 1024;
+    if (r->footprint > s->budget) {
+        delete r;
+        return LGT_E_OOM;
+    }
+    r->ticket = s->next_ticket++;
+    r->t_submit = Clock::now();
+    *ticket = r->ticket;
+    s->results[r->ticket] = lgt_result{};
+    s->pending.push_back(r);
+    lk.unlock();
+    s->cv_work.notify_one();
+    return LGT_OK;
+}
+
+lgt_status lgt_server_poll(lgt_server *s, uint64_t ticket, lgt_result *out)
+{
+    if (!s || !out) return LGT_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->results.find(ticket);
+    if (it == s->results.end()) return LGT_E_INVALID;
+    *out = it->second;
+    return LGT_OK;
+}
+
+lgt_status lgt_server_wait(lgt_server *s, uint64_t ticket, double timeout_ms, lgt_result *out)
+{
+    if (!s || !out) return LGT_E_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto ready = [&] {
+        auto it = s->results.find(ticket);
+        return it == s->results.end() || it->second.done;
+    };
+    if (timeout_ms < 0) s->cv_done.wait(lk, ready);
+    else s->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), ready);
+    auto it = s->results.find(ticket);
+    if (it == s->results.end()) return LGT_E_INVALID;
+    *out = it->second;
+    return it->second.done ? LGT_OK : LGT_E_BUSY;
+}
+
+lgt_status lgt_server_destroy(lgt_server *s)
+{
+    if (!s) return LGT_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    for (auto &kv : s->shapes)
+        if (kv.second.ptab_dev) (void)hipFree(kv.second.ptab_dev);
+    if (s->inst_dev) (void)hipFree(s->inst_dev);
+    if (s->partials) (void)hipFree(s->partials);
+    if (s->masks_dev) (void)hipFree(s->masks_dev);
+    if (s->stage) (void)hipHostFree(s->stage);
+    (void)hipStreamDestroy(s->stream);
+    delete s;
+    return LGT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI (no GPU work): exports, lattice geometry, validation."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_08020_amd import lgt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lgt.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lgt_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for core in ("lgt_create", "lgt_evolve", "lgt_measure", "lgt_sample"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lgt.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", lgt.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(lgt_[a-z_]+)$", out, flags=re.M))
+    for name in _declared():
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_binding_covers_every_symbol():
+    bound = {s[0] for s in lgt._SIGNATURES}
+    assert set(_declared()) == bound
+    for name in _declared():
+        assert callable(getattr(lgt, name))
+
+
+LATTICES = [(2, (2, 2)), (2, (3, 3)), (2, (3, 4)), (2, (2, 7)), (2, (3, 5)), (2, (4, 4)),
+            (3, (2, 2, 2))]
+
+
+@pytest.mark.parametrize("d,L", LATTICES)
+def test_library_lattice_matches_oracle(d, L):
+    """The two independently written lattice builders agree link for link."""
+    q = lgt.lgt_lattice_query(d, L)
+    ol = oracle.Lattice(d, L)
+    assert (q["n_links"], q["n_plaq"], q["n_sites"]) == (ol.n_links, ol.n_plaq, ol.n_sites)
+    assert np.array_equal(q["plaq_links"], ol.plaq)
+    stars = np.array([sum(1 << int(x) for x in s) for s in ol.stars], dtype=np.uint64)
+    assert np.array_equal(q["star_masks"], stars)
+
+
+def test_validation_without_gpu():
+    with pytest.raises(lgt.LgtError) as e:
+        lgt.lgt_lattice_query(4, [2, 2, 2, 2])
+    assert e.value.status == lgt.LGT_E_INVALID
+    with pytest.raises(lgt.LgtError) as e:
+        lgt.lgt_lattice_query(2, [1, 3])
+    assert e.value.status == lgt.LGT_E_INVALID
+    with pytest.raises(lgt.LgtError) as e:
+        lgt.lgt_lattice_query(3, [3, 3, 3])          # 81 links: too many for one state
+    assert e.value.status == lgt.LGT_E_UNSUPPORTED
+    with pytest.raises(lgt.LgtError) as e:
+        lgt.lgt_create(2, [2, 2], periodic=0)         # open boundaries are not implemented
+    assert e.value.status == lgt.LGT_E_UNSUPPORTED
+    with pytest.raises(lgt.LgtError) as e:
+        lgt.lgt_create(2, [2, 2], periodic=1, dtype=7)
+    assert e.value.status == lgt.LGT_E_INVALID
+    with pytest.raises(lgt.LgtError):
+        lgt.lgt_server_create(0, 4, 10)
+
+
+def test_struct_layouts():
+    """ctypes mirrors of the ABI structs have the C layout (LP64)."""
+    import ctypes
+    assert ctypes.sizeof(lgt.lgt_schedule) == 80
+    assert lgt.lgt_schedule.cx.offset == 64
+    assert ctypes.sizeof(lgt.lgt_observable) == 32
+    assert lgt.lgt_info_t.state_bytes.offset == 32
+    assert lgt.lgt_request.sched.offset == 24

@@ -1,0 +1,364 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded inputs.
+
+Tolerances: complex128 amplitudes and observables within 1e-10 of the oracle;
+complex64 states within infidelity 1e-5 and observables within 1e-4 of the
+complex128 oracle (the precision targets of the engine).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.dual import DualIsing
+from paper_1910_08020_amd import lgt
+from tests.harness import get_state, gpu_ctx, gpu_evolve, infidelity, oracle_evolve
+
+pytestmark = pytest.mark.gpu
+
+C64, C128 = lgt.LGT_C64, lgt.LGT_C128
+TROT, SYM = lgt.LGT_ORDER_TROTTER, lgt.LGT_ORDER_SYMMETRIC
+
+# every lattice shape with <= 24 links, covering the on-chip kernel (8, 12 links),
+# the low pass alone plus one register pass (16, 18, 20) and two or three (24)
+SHAPES = [(2, (2, 2)), (2, (2, 3)), (2, (2, 4)), (2, (3, 3)), (2, (2, 5)), (2, (3, 4)),
+          (3, (2, 2, 2))]
+
+
+def _ids(shapes):
+    return ["x".join(map(str, L)) for _, L in shapes]
+
+
+@pytest.mark.parametrize("d,L", SHAPES, ids=_ids(SHAPES))
+def test_lattice_info_matches_oracle(d, L):
+    ol = oracle.Lattice(d, L)
+    with gpu_ctx(d, L, C64) as ctx:
+        info = lgt.lgt_info(ctx)
+        assert np.array_equal(info["plaq_links"], ol.plaq)
+        for s in range(ol.n_sites):
+            assert int(info["star_masks"][s]) == sum(1 << int(q) for q in ol.stars[s])
+        if d == 2 and min(L) >= 3:
+            m = lgt.lgt_wilson_mask(ctx, 0, 0, 1, 2, 2)
+            assert m == sum(1 << int(q) for q in ol.rect_loop(0, 0, 1, 2, 2))
+        for mu in range(d):
+            assert lgt.lgt_line_mask(ctx, 0, mu) == sum(1 << int(q) for q in ol.line(0, mu))
+
+
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+@pytest.mark.parametrize("d,L", [(2, (2, 2)), (2, (3, 3)), (3, (2, 2, 2))],
+                         ids=["2x2", "3x3", "2x2x2"])
+def test_init_states(d, L, dtype):
+    ol = oracle.Lattice(d, L)
+    tol = 1e-7 if dtype == C64 else 1e-15
+    with gpu_ctx(d, L, dtype) as ctx:
+        assert np.max(np.abs(get_state(ctx) - oracle.plus_state(ol.N))) < tol
+        lgt.lgt_reset(ctx, lgt.LGT_INIT_BASIS, 5)
+        assert np.max(np.abs(get_state(ctx) - oracle.basis_state(ol.N, 5))) < tol
+        lgt.lgt_reset(ctx, lgt.LGT_INIT_ZGROUND, 0)
+        assert np.max(np.abs(get_state(ctx) - oracle.zground_state(ol))) < tol
+
+
+@pytest.mark.parametrize("order", [TROT, SYM], ids=["trotter", "symmetric"])
+@pytest.mark.parametrize("d,L", SHAPES, ids=_ids(SHAPES))
+def test_fused_c128_matches_oracle(d, L, order):
+    ol = oracle.Lattice(d, L)
+    psi0 = workloads.random_state(ol.N, stream=ol.N)
+    n = 6 if ol.N >= 24 else 25
+    T, lam = 0.05 * n, 0.85
+    got = gpu_evolve(d, L, C128, T, n, lam, 1.0, order, state=psi0)
+    want = oracle_evolve(ol, T, n, lam, 1.0, order, state=psi0)
+    assert np.max(np.abs(got - want)) < 1e-10
+
+
+@pytest.mark.parametrize("order", [TROT, SYM], ids=["trotter", "symmetric"])
+@pytest.mark.parametrize("d,L", SHAPES, ids=_ids(SHAPES))
+def test_fused_c64_matches_oracle(d, L, order):
+    ol = oracle.Lattice(d, L)
+    n = 6 if ol.N >= 24 else 40
+    T, lam = 0.05 * n, 1.3
+    got = gpu_evolve(d, L, C64, T, n, lam, 1.0, order)
+    want = oracle_evolve(ol, T, n, lam, 1.0, order)
+    assert infidelity(got, want) < 1e-5
+    for p in ol.plaq[:6]:
+        assert abs(oracle.expect_z(got, ol.N, p) - oracle.expect_z(want, ol.N, p)) < 1e-4
+
+
+def test_large_rotation_angle_branch():
+    """|tan a| > 1 takes the cot form of the factored link rotation."""
+    ol = oracle.Lattice(2, (3, 3))
+    psi0 = workloads.random_state(ol.N, stream=99)
+    for h_x in (25.0, -31.0):   # dt h_x = 1.25 and -1.55 rad
+        got = gpu_evolve(2, (3, 3), C128, 0.5, 10, h_x, 1.0, SYM, state=psi0)
+        want = oracle_evolve(ol, 0.5, 10, h_x, 1.0, SYM, state=psi0)
+        assert np.max(np.abs(got - want)) < 1e-10
+
+
+@pytest.mark.parametrize("order", [TROT, SYM], ids=["trotter", "symmetric"])
+@pytest.mark.parametrize("d,L,n", [(2, (2, 2), 12), (2, (3, 3), 3), (3, (2, 2, 2), 1)],
+                         ids=["2x2", "3x3", "2x2x2"])
+def test_circuit_form_matches_oracle(d, L, n, order):
+    """eq. (ara) gate by gate on the GPU equals the oracle's fused evolution."""
+    ol = oracle.Lattice(d, L)
+    psi0 = workloads.random_state(ol.N, stream=7)
+    T = 0.05 * n
+    got = gpu_evolve(d, L, C128, T, n, 0.6, 1.0, order, form=lgt.LGT_FORM_CIRCUIT, state=psi0)
+    want = oracle_evolve(ol, T, n, 0.6, 1.0, order, state=psi0)
+    assert np.max(np.abs(got - want)) < 1e-10
+
+
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+@pytest.mark.parametrize("d,L", [(2, (2, 2)), (2, (3, 3)), (3, (2, 2, 2))],
+                         ids=["2x2", "3x3", "2x2x2"])
+def test_measure_matches_oracle(d, L, dtype):
+    ol = oracle.Lattice(d, L)
+    N = ol.N
+    psi = workloads.random_state(N, stream=3 + N)
+    if dtype == C64:
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    tol = 1e-10
+    with gpu_ctx(d, L, dtype, psi) as ctx:
+        n2 = oracle.norm2(psi, N)
+        assert abs(lgt.lgt_measure(ctx, lgt.LGT_OBS_NORM)[0] - n2) < tol
+        plaq = lgt.lgt_measure(ctx, lgt.LGT_OBS_PLAQ)[: ol.n_plaq]
+        assert np.max(np.abs(plaq - [oracle.expect_z(psi, N, p) for p in ol.plaq])) < tol
+        sz = lgt.lgt_measure(ctx, lgt.LGT_OBS_SIGMAZ)[:N]
+        assert np.max(np.abs(sz - [oracle.expect_z(psi, N, [q]) for q in range(N)])) < tol
+        sx = lgt.lgt_measure(ctx, lgt.LGT_OBS_SIGMAX)[:N]
+        assert np.max(np.abs(sx - [oracle.expect_x(psi, N, [q]) for q in range(N)])) < tol
+        st = lgt.lgt_measure(ctx, lgt.LGT_OBS_STAR)[: ol.n_sites]
+        assert np.max(np.abs(st - [oracle.expect_x(psi, N, s) for s in ol.stars])) < tol
+        loops = [ol.line(0, mu) for mu in range(d)]
+        if d == 2 and min(L) >= 3:
+            loops.append(ol.rect_loop(0, 0, 1, 2, 2))
+        masks = [sum(1 << int(q) for q in lp) for lp in loops]
+        wz = lgt.lgt_measure(ctx, lgt.LGT_OBS_Z, masks=masks)[: len(masks)]
+        assert np.max(np.abs(wz - [oracle.expect_z(psi, N, lp) for lp in loops])) < tol
+        wx = lgt.lgt_measure(ctx, lgt.LGT_OBS_X, masks=masks)[: len(masks)]
+        assert np.max(np.abs(wx - [oracle.expect_x(psi, N, lp) for lp in loops])) < tol
+        e = lgt.lgt_measure(ctx, lgt.LGT_OBS_ENERGY, cx=0.7, cz=1.3)[0]
+        want = -0.7 * sum(oracle.expect_x(psi, N, [q]) for q in range(N)) - 1.3 * sum(
+            oracle.expect_z(psi, N, p) for p in ol.plaq)
+        assert abs(e - want) < tol
+        dos = lgt.lgt_measure(ctx, lgt.LGT_OBS_ZDOS)[: ol.n_plaq + 1]
+        assert np.max(np.abs(dos - oracle.zdos(psi, ol))) < tol
+        with pytest.raises(lgt.LgtError) as ex:
+            lgt.lgt_measure(ctx, lgt.LGT_OBS_PLAQ, out_len=ol.n_plaq - 1)
+        assert ex.value.status == lgt.LGT_E_INVALID
+
+
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+@pytest.mark.parametrize("d,L", [(2, (2, 2)), (2, (3, 3))], ids=["2x2", "3x3"])
+def test_sample_matches_oracle(d, L, dtype):
+    """Same SplitMix64 stream and inverse CDF: identical shots except where a draw
+    falls within rounding of a cumulative-probability boundary."""
+    ol = oracle.Lattice(d, L)
+    psi = workloads.random_state(ol.N, stream=11)
+    if dtype == C64:
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    with gpu_ctx(d, L, dtype, psi) as ctx:
+        shots = lgt.lgt_sample(ctx, 20000, 424242)
+    want = oracle.sample(psi, ol.N, 20000, 424242)
+    cdf = oracle.cdf(psi, ol.N)
+    bad = np.nonzero(shots != want)[0]
+    for i in bad:
+        u = oracle.uniform(424242, int(i)) * cdf[-1]
+        assert abs(cdf[int(want[i])] - u) < 1e-12 or abs(cdf[int(shots[i])] - u) < 1e-12
+    assert len(bad) <= 2
+
+
+@pytest.mark.parametrize("order", [TROT, SYM], ids=["trotter", "symmetric"])
+def test_split_evolve_equals_single_call(order):
+    """Resuming at a step boundary (checkpoint/resume) gives the same state."""
+    d, L = 2, (3, 3)
+    with gpu_ctx(d, L, C128) as a, gpu_ctx(d, L, C128) as b:
+        s = lgt.make_schedule(5.0, 100, 0.9, 1.0)
+        lgt.lgt_evolve(a, s, order, lgt.LGT_FORM_FUSED, 0, 100)
+        lgt.lgt_evolve(b, s, order, lgt.LGT_FORM_FUSED, 0, 37)
+        lgt.lgt_evolve(b, s, order, lgt.LGT_FORM_FUSED, 37, 63)
+        assert np.max(np.abs(get_state(a) - get_state(b))) < 1e-12
+
+
+def test_schedule_validation_and_edges():
+    with gpu_ctx(2, (2, 2), C128) as ctx:
+        s = lgt.make_schedule(1.0, 10, 1.0, 1.0)
+        psi0 = get_state(ctx)
+        lgt.lgt_evolve(ctx, s, TROT, lgt.LGT_FORM_FUSED, 4, 0)     # empty range: no-op
+        assert np.array_equal(get_state(ctx), psi0)
+        for first, count in ((0, 11), (-1, 2), (10, 1)):
+            with pytest.raises(lgt.LgtError) as e:
+                lgt.lgt_evolve(ctx, s, TROT, lgt.LGT_FORM_FUSED, first, count)
+            assert e.value.status == lgt.LGT_E_INVALID
+        with pytest.raises(lgt.LgtError):
+            lgt.lgt_evolve(ctx, lgt.make_schedule(0.0, 10), TROT, lgt.LGT_FORM_FUSED, 0, 1)
+        with pytest.raises(lgt.LgtError):
+            lgt.lgt_evolve(ctx, s, 3, lgt.LGT_FORM_FUSED, 0, 1)
+        # the last step alone
+        lgt.lgt_evolve(ctx, s, SYM, lgt.LGT_FORM_FUSED, 9, 1)
+        ol = oracle.Lattice(2, (2, 2))
+        want = oracle_evolve(ol, 1.0, 10, 1.0, 1.0, SYM, first=9, count=1)
+        assert np.max(np.abs(get_state(ctx) - want)) < 1e-12
+
+
+def test_coupling_ramp_paper_form():
+    """H = Z + g X with g ramping 0 -> 2 (Sec. 2.2), from the projected Z ground state."""
+    ol = oracle.Lattice(2, (3, 3))
+    n, T = 200, 10.0
+    with gpu_ctx(2, (3, 3), C128) as ctx:
+        lgt.lgt_reset(ctx, lgt.LGT_INIT_ZGROUND, 0)
+        s = lgt.make_schedule(T, n, ramp=lgt.LGT_RAMP_COUPLING, g0=0.0, g1=2.0)
+        lgt.lgt_evolve(ctx, s, SYM, lgt.LGT_FORM_FUSED, 0, n)
+        got = get_state(ctx)
+    dt, cx, cz = oracle.schedule_coupling_ramp(T, n, 0.0, 2.0)
+    want = oracle.evolve(oracle.zground_state(ol), ol, dt, cx, cz, 2)
+    assert np.max(np.abs(got - want)) < 1e-10
+
+
+def test_explicit_schedule():
+    ol = oracle.Lattice(2, (2, 3))
+    g = np.random.default_rng(5)
+    cx, cz = g.uniform(0, 2, 30), g.uniform(-1, 1, 30)
+    with gpu_ctx(2, (2, 3), C128) as ctx:
+        s = lgt.make_schedule(1.5, 30, ramp=lgt.LGT_RAMP_EXPLICIT, cx=cx, cz=cz)
+        lgt.lgt_evolve(ctx, s, TROT, lgt.LGT_FORM_FUSED, 0, 30)
+        got = get_state(ctx)
+    want = oracle.evolve(oracle.plus_state(ol.N), ol, 0.05, cx, cz, 1)
+    assert np.max(np.abs(got - want)) < 1e-10
+
+
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+@pytest.mark.parametrize("d,L", [(2, (2, 2)), (2, (3, 3))], ids=["2x2", "3x3"])
+def test_batch_equals_single_instances(d, L, dtype):
+    lams = [0.1 + 0.095 * i for i in range(21)]
+    n = 60
+    ctxs = [lgt.lgt_create(d, list(L), 1, dtype) for _ in lams]
+    try:
+        scheds = [lgt.make_schedule(0.05 * n, n, lam, 1.0) for lam in lams]
+        lgt.lgt_batch_evolve(ctxs, scheds, [SYM] * len(lams), 0, n)
+        batched = [get_state(c) for c in ctxs]
+    finally:
+        for c in ctxs:
+            lgt.lgt_destroy(c)
+    for lam, psi in zip(lams, batched):
+        single = gpu_evolve(d, L, dtype, 0.05 * n, n, lam, 1.0, SYM)
+        assert np.array_equal(single, psi)
+
+
+def test_config1_full_run():
+    """2x2, first order, 1000 steps, T = 50, complex128: energy, <U_p>, <G_i>."""
+    w = workloads.CONFIG1
+    ol = oracle.Lattice(w.d, w.L)
+    with gpu_ctx(w.d, w.L, C128) as ctx:
+        s = lgt.make_schedule(w.T, w.n_steps, 1.0, 1.0)
+        lgt.lgt_evolve(ctx, s, TROT, lgt.LGT_FORM_FUSED, 0, w.n_steps)
+        e = lgt.lgt_measure(ctx, lgt.LGT_OBS_ENERGY, cx=1.0, cz=1.0)[0]
+        plaq = lgt.lgt_measure(ctx, lgt.LGT_OBS_PLAQ)[: ol.n_plaq]
+        stars = lgt.lgt_measure(ctx, lgt.LGT_OBS_STAR)[: ol.n_sites]
+    psi = oracle_evolve(ol, w.T, w.n_steps, 1.0, 1.0, TROT)
+    r = oracle.readout(psi, ol, 1.0, 1.0)
+    assert abs(e - r["energy"]) < 1e-10
+    assert np.max(np.abs(plaq - r["plaq"])) < 1e-10
+    assert np.max(np.abs(stars - r["stars"])) < 1e-10
+
+
+@pytest.mark.parametrize("lam", [0.1, 1.05, 2.0])
+def test_config2_lambda_full_run(lam):
+    """3x3, symmetric, 2000 steps, T = 100: complex64 GPU against the complex128 oracle."""
+    w = workloads.CONFIG2
+    ol = oracle.Lattice(w.d, w.L)
+    got = gpu_evolve(w.d, w.L, C64, w.T, w.n_steps, lam, 1.0, SYM)
+    want = oracle_evolve(ol, w.T, w.n_steps, lam, 1.0, SYM)
+    assert infidelity(got, want) < 1e-5
+    N = ol.N
+    w22 = ol.rect_loop(0, 0, 1, 2, 2)
+    for links in list(ol.plaq) + [w22]:
+        assert abs(oracle.expect_z(got, N, links) - oracle.expect_z(want, N, links)) < 1e-4
+    gv = max(abs(1 - oracle.expect_x(got, N, s)) for s in ol.stars)
+    assert gv < 1e-4
+
+
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+def test_config3_full_size_steps(dtype):
+    """2x2x2 (24 links), symmetric, the first steps of the 2000-step run at lambda = 2."""
+    w = workloads.CONFIG3
+    ol = oracle.Lattice(w.d, w.L)
+    n = 4
+    got = gpu_evolve(w.d, w.L, dtype, w.T, w.n_steps, 2.0, 1.0, SYM, first=0, count=n)
+    want = oracle_evolve(ol, w.T, w.n_steps, 2.0, 1.0, SYM, first=0, count=n)
+    if dtype == C128:
+        assert np.max(np.abs(got - want)) < 1e-10
+    else:
+        assert infidelity(got, want) < 1e-5
+
+
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+def test_config3_invariants_full_run(dtype):
+    """All 2000 steps at lambda = 0.5: norm, Gauss law, <sigma^z_l> = 0 (GPU only)."""
+    w = workloads.CONFIG3
+    with gpu_ctx(w.d, w.L, dtype) as ctx:
+        s = lgt.make_schedule(w.T, w.n_steps, 0.5, 1.0)
+        lgt.lgt_evolve(ctx, s, SYM, lgt.LGT_FORM_FUSED, 0, w.n_steps)
+        tol = 1e-4 if dtype == C64 else 1e-10
+        assert abs(lgt.lgt_measure(ctx, lgt.LGT_OBS_NORM)[0] - 1) < tol
+        stars = lgt.lgt_measure(ctx, lgt.LGT_OBS_STAR)[:8]
+        assert np.max(np.abs(stars - 1)) < tol
+        sz = lgt.lgt_measure(ctx, lgt.LGT_OBS_SIGMAZ)[:24]
+        assert np.max(np.abs(sz)) < tol
+
+
+@pytest.mark.parametrize("d,L", [(2, (2, 7)), (2, (3, 5)), (2, (4, 4))], ids=["2x7", "3x5", "4x4"])
+def test_large_2d_against_dual_ising(d, L):
+    """28-32 links: observables against the exact dual transverse-field Ising image."""
+    ol = oracle.Lattice(d, L)
+    n, lam = 30, 1.0
+    dt, cx, cz = oracle.schedule_plaquette_ramp(0.05 * n, n, lam, 1.0)
+    D = DualIsing(ol.plaq, ol.N)
+    phi = D.evolve(D.ghz(), dt, cx, cz, 2)
+    want_plaq = np.array([D.expect_tx(phi, [p]) for p in range(ol.n_plaq)])
+    want_sx = np.array([D.expect_bond(phi, l) for l in range(ol.N)])
+    for dtype, tol in ((C64, 1e-4), (C128, 1e-10)):
+        with gpu_ctx(d, L, dtype) as ctx:
+            s = lgt.make_schedule(0.05 * n, n, lam, 1.0)
+            lgt.lgt_evolve(ctx, s, SYM, lgt.LGT_FORM_FUSED, 0, n)
+            plaq = lgt.lgt_measure(ctx, lgt.LGT_OBS_PLAQ)[: ol.n_plaq]
+            sx = lgt.lgt_measure(ctx, lgt.LGT_OBS_SIGMAX)[: ol.N]
+            stars = lgt.lgt_measure(ctx, lgt.LGT_OBS_STAR)[: ol.n_sites]
+            assert np.max(np.abs(plaq - want_plaq)) < tol
+            assert np.max(np.abs(sx - want_sx)) < tol
+            assert np.max(np.abs(stars - 1)) < tol
+
+
+def test_server_alone_equals_mix():
+    """Continuous batching: each run's result is the same alone and in the mix."""
+    reqs = workloads.serving_stream(12, rate_per_s=1e6, steps_lo=40, steps_hi=120)
+
+    def make(r):
+        q = lgt.lgt_request()
+        q.d = r.d
+        for i, x in enumerate(r.L):
+            q.L[i] = x
+        q.dtype = C64
+        q.sched = lgt.make_schedule(0.05 * r.n_steps, r.n_steps, r.lam, 1.0)
+        q.order = r.order
+        return q
+
+    srv = lgt.lgt_server_create(8 << 30, 16, 25)
+    try:
+        tickets = [lgt.lgt_server_submit(srv, make(r)) for r in reqs]
+        mixed = [lgt.lgt_server_wait(srv, t, 60000.0) for t in tickets]
+    finally:
+        lgt.lgt_server_destroy(srv)
+    for r, res in zip(reqs, mixed):
+        assert res.done == 1 and res.status == lgt.LGT_OK
+        srv = lgt.lgt_server_create(8 << 30, 1, 25)
+        try:
+            alone = lgt.lgt_server_wait(srv, lgt.lgt_server_submit(srv, make(r)), 60000.0)
+        finally:
+            lgt.lgt_server_destroy(srv)
+        assert abs(alone.energy - res.energy) < 1e-9
+        assert abs(alone.plaq_mean - res.plaq_mean) < 1e-9
+        # and against the direct path
+        with gpu_ctx(r.d, r.L, C64) as ctx:
+            s = lgt.make_schedule(0.05 * r.n_steps, r.n_steps, r.lam, 1.0)
+            lgt.lgt_evolve(ctx, s, r.order, lgt.LGT_FORM_FUSED, 0, r.n_steps)
+            e = lgt.lgt_measure(ctx, lgt.LGT_OBS_ENERGY, cx=r.lam, cz=1.0)[0]
+        assert abs(e - res.energy) < 1e-6
+        assert res.gauss_violation < 1e-4
