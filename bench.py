@@ -196,8 +196,6 @@ def main():
                                    "measured (multi-GPU sharding is a design note)"}))
         sys.exit(2)
     lgt = _lgt()
-    import torch  # device and stream plumbing only
-    torch.cuda.init()
 
     w = workloads.CONFIG3
     ctx = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64)
@@ -209,13 +207,12 @@ def main():
         run_job(lgt, ctx, w, masks, n_sites, n_plaq)
     lgt.lgt_sync(ctx)
     lgt.lgt_set_profiling(ctx, True)
-    torch.cuda.synchronize()
+    lgt.lgt_sync(ctx)
     t0 = time.perf_counter()
     results = None
     for _ in range(args.steps):
         results = run_job(lgt, ctx, w, masks, n_sites, n_plaq)
     lgt.lgt_sync(ctx)
-    torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stats = lgt.lgt_kernel_stats(ctx)
     lgt.lgt_set_profiling(ctx, False)

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -208,22 +209,48 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 namespace lgt {
 
-PassPlan plan_passes(int n_links, int dtype)
+PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
 {
     PassPlan p;
-    if (n_links < 12) return p;   // handled on chip by the small-state kernel
-    p.low_bits = 12;
-    p.n_passes = 1;
-    int rest = n_links - 12;
-    const int hmax = dtype == LGT_C64 ? 6 : 5;
-    int nh = (rest + hmax - 1) / hmax;
-    int q = 12;
-    for (int i = 0; i < nh; ++i) {
-        int h = rest / nh + (i < rest % nh ? 1 : 0);
-        p.hi_q0[i] = q;
-        p.hi_h[i] = h;
+    if (n_links <= 12) return p;   // handled on chip by the small-state kernel
+    const int low = dtype == LGT_C64 ? 14 : 13;
+    // too few low tiles to fill the GPU: the 12-bit plan gives 4x more workgroups.  The
+    // choice depends on the lattice only, so batched and single runs round identically.
+    (void)n_inst;
+    if (n_links < low || (1 << (n_links - low)) < 64) plan = 1;
+    if (plan == 0) {
+        PassPlan t = plan_passes(n_links, dtype, 2, n_inst);
+        for (int i = 1; i < t.n_passes; ++i)
+            if (t.pass[i].kind == PASS_TILE_HIGH &&
+                !pass_offsets_fit(dtype, n_links, 0, t.pass[i].q0, t.pass[i].h))
+                plan = 1;
+        if (plan == 0) return t;
+    }
+    if (plan == 1) {
+        // 12-bit low tile, then register passes of at most 6 (complex64) / 5 bits
+        p.pass[p.n_passes++] = Pass{PASS_LOW12, 0, 12};
+        const int rest = n_links - 12, hmax = dtype == LGT_C64 ? 6 : 5;
+        const int nh = (rest + hmax - 1) / hmax;
+        int q = 12;
+        for (int i = 0; i < nh; ++i) {
+            const int h = rest / nh + (i < rest % nh ? 1 : 0);
+            p.pass[p.n_passes++] = Pass{PASS_HIGH_REG, q, h};
+            q += h;
+        }
+        return p;
+    }
+    // persistent tile passes: one low tile, then high tiles of up to 10 rotated bits;
+    // chunks the tile pass cannot take go to the register pass
+    p.pass[p.n_passes++] = Pass{PASS_TILE_LOW, 0, low};
+    int rest = n_links - low, q = low;
+    const int reg_max = dtype == LGT_C64 ? 6 : 5;
+    while (rest > 0) {
+        int h = rest < 10 ? rest : 10;
+        while (h > reg_max && pass_tile_bits(dtype, 0, h) < 0) --h;
+        const bool tile = pass_tile_bits(dtype, 0, h) >= 0 && h > 4;
+        p.pass[p.n_passes++] = Pass{tile ? PASS_TILE_HIGH : PASS_HIGH_REG, q, h};
         q += h;
-        ++p.n_passes;
+        rest -= h;
     }
     return p;
 }
@@ -234,8 +261,8 @@ namespace lgt {
 
 // enqueue `count` fused substeps of n_inst instances whose pointers sit in dev_inst
 hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_inst, int n_inst,
-                               int count, int pre_first, int post_off, hipStream_t st,
-                               void *prof_ctx)
+                               int count, int pre_first, int post_off, const uint8_t *forms,
+                               hipStream_t st, void *prof_ctx)
 {
     lgt_ctx *pc = (lgt_ctx *)prof_ctx;
     auto run = [&](int kf, auto &&launch) -> hipError_t {
@@ -248,21 +275,39 @@ hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_
             return launch_small(dtype, dev_inst, n_inst, n, count, pre_first >= 0 ? 1 : 0, n_plaq, st);
         });
     }
-    const PassPlan plan = plan_passes(n, dtype);
+    static const int plan_sel = [] {
+        const char *e = std::getenv("LGT_PASS_PLAN");
+        return e ? std::atoi(e) : 0;
+    }();
+    const PassPlan plan = plan_passes(n, dtype, plan_sel, n_inst);
     for (int j = 0; j < count; ++j) {
+        const int fm = forms ? (forms[j] ? forms[j] : 1) : 3;
         for (int p = 0; p < plan.n_passes; ++p) {
+            const Pass &ps = plan.pass[p];
             const bool last = (p == plan.n_passes - 1);
             const int post = last ? j + post_off : -1;
+            const int pre = (p == 0 && j == 0) ? pre_first : -1;
             hipError_t e;
-            if (p == 0) {
-                const int pre = (j == 0) ? pre_first : -1;
+            switch (ps.kind) {
+            case PASS_LOW12:
                 e = run(KF_LOW, [&] {
-                    return launch_low(dtype, dev_inst, n_inst, n, plan.low_bits, j, pre, post, n_plaq, st);
+                    return launch_low(dtype, dev_inst, n_inst, n, 12, j, pre, post, n_plaq, st);
                 });
-            } else {
+                break;
+            case PASS_TILE_LOW:
+                e = run(KF_TILE_LOW, [&] {
+                    return launch_tile(dtype, dev_inst, n_inst, n, 1, 0, 0, j, pre, post, n_plaq, fm, st);
+                });
+                break;
+            case PASS_TILE_HIGH:
+                e = run(KF_TILE_HIGH, [&] {
+                    return launch_tile(dtype, dev_inst, n_inst, n, 0, ps.q0, ps.h, j, pre, post, n_plaq, fm, st);
+                });
+                break;
+            default:
+                if (pre >= 0) return hipErrorInvalidValue;   // register passes never come first
                 e = run(KF_HIGH, [&] {
-                    return launch_high(dtype, dev_inst, n_inst, n, plan.hi_q0[p - 1], plan.hi_h[p - 1], j,
-                                       post, n_plaq, st);
+                    return launch_high(dtype, dev_inst, n_inst, n, ps.q0, ps.h, j, post, n_plaq, st);
                 });
             }
             if (e != hipSuccess) return e;
@@ -274,10 +319,17 @@ hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_
 }  // namespace lgt
 
 static hipError_t enqueue_fused(lgt_ctx *c, const DevInst *dev_inst, int n_inst, int count,
-                                int pre_phase)
+                                int pre_phase, const uint8_t *forms)
 {
     return enqueue_fused_steps(c->dtype, c->lat.n_links, c->lat.n_plaq, dev_inst, n_inst, count,
-                               pre_phase ? 0 : -1, pre_phase, c->stream, c);
+                               pre_phase ? 0 : -1, pre_phase, forms, c->stream, c);
+}
+
+// bit 0: tan form (u == 1) of the factored link rotation, bit 1: cot form
+static void or_forms(const StepTables &st, std::vector<uint8_t> &forms)
+{
+    if (forms.size() < (size_t)st.n_steps) forms.resize(st.n_steps, 0);
+    for (int j = 0; j < st.n_steps; ++j) forms[j] |= (st.rot_u[j] == 1.0) ? 1 : 2;
 }
 
 static lgt_status create_common(int d, const int *L, int periodic, lgt_dtype dtype, void *buf,
@@ -560,7 +612,9 @@ lgt_status lgt_evolve(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, lg
     HIPCHK(c, hipMemcpyAsync(c->ph_dev, stg + rb, tb.ph_bytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->inst_dev, stg + rb + pb, sizeof(DevInst), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipEventRecord(c->stage_free, c->stream));
-    HIPCHK(c, enqueue_fused(c, c->inst_dev, 1, (int)count, st.pre_phase));
+    std::vector<uint8_t> forms;
+    or_forms(st, forms);
+    HIPCHK(c, enqueue_fused(c, c->inst_dev, 1, (int)count, st.pre_phase, forms.data()));
     return LGT_OK;
 }
 
@@ -793,12 +847,14 @@ lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule
     // every instance's tables in one staging block
     std::vector<Tables> tbs(n_inst);
     StepTables st;
+    std::vector<uint8_t> forms;
     for (int i = 0; i < n_inst; ++i) {
         double dt;
         std::vector<double> cx, cz;
         std::string why = schedule_coeffs(&scheds[i], first_step, count, dt, cx, cz);
         if (!why.empty()) return fail(nullptr, LGT_E_INVALID, why);
         make_tables(c0->lat, c0->dtype, dt, cx, cz, orders[i], st, tbs[i]);
+        or_forms(st, forms);
     }
     const size_t rb = align256(tbs[0].rot_bytes), pb = align256(tbs[0].ph_bytes);
     const size_t ib = align256(sizeof(DevInst) * n_inst);
@@ -827,7 +883,8 @@ lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule
     if (hipMemcpyAsync(dev, stg, total, hipMemcpyHostToDevice, c0->stream) != hipSuccess ||
         hipEventRecord(c0->stage_free, c0->stream) != hipSuccess)
         return fail(nullptr, LGT_E_DEVICE, "batch upload");
-    hipError_t e = enqueue_fused(c0, (const DevInst *)(dev + (rb + pb) * n_inst), n_inst, (int)count, st.pre_phase);
+    hipError_t e = enqueue_fused(c0, (const DevInst *)(dev + (rb + pb) * n_inst), n_inst, (int)count,
+                                 st.pre_phase, forms.data());
     if (e != hipSuccess) return fail(nullptr, LGT_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     // the other contexts must not race ahead of the shared launches
     for (int i = 1; i < n_inst; ++i)

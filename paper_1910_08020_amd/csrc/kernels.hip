@@ -15,6 +15,8 @@
 // P(r) from the per-link plaquette sets; the phase is table[popcount(P)].
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lgt_internal.hpp"
 
 namespace lgt {
@@ -170,6 +172,210 @@ __global__ __launch_bounds__(kLowThreads) void k_low(const DevInst *__restrict__
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) psi[base + ((uint64_t)t << 4) + r] = v[r];
+}
+
+// ---------------------------------------------------------------------------
+// persistent tile pass.  A workgroup of 2^W waves owns tiles of 2^(10+W) amplitudes
+// and walks over the tiles of its instance with a stride of gridDim.x, loading the
+// next tile into registers while it works on the current one.
+//
+// Layout A (load):  tile bit 0..5 = lane, 6..5+W = wave, 6+W..9+W = register.
+// Layout B (store): tile bit 0..5 = lane, 6..5+W = low W register bits,
+//                   6+W..5+2W = wave, 6+2W..9+W = high 4-W register bits.
+// Lanes always sit on the lowest tile bits, so every LDS access is a run of 64
+// consecutive slots (no bank conflicts) and every global access is coalesced.
+// Rotations: register bits in registers, lane bits across lanes (DPP within a row
+// of 16, shuffles for 16 and 32), wave bits in registers after one LDS exchange.
+//   low tile:  tile bit i = index bit i, all 10+W bits rotated.
+//   high tile: tile bits 0..CB-1 = index bits 0..CB-1 (rows of 128 bytes, not
+//              rotated), tile bit i >= CB = index bit hb + i - CB (rotated).
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL,
+                                                              0xF, 0xF, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double x)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// value held by lane ^ (1 << B)
+template <int B, typename T>
+__device__ __forceinline__ T lane_partner(T x)
+{
+    if constexpr (B == 0) return dpp_f<0xB1>(x);                 // quad_perm [1,0,3,2]
+    else if constexpr (B == 1) return dpp_f<0x4E>(x);            // quad_perm [2,3,0,1]
+    else if constexpr (B == 2) return dpp_f<0x1B>(dpp_f<0x141>(x));  // half-row mirror, then ^3
+    else if constexpr (B == 3) return dpp_f<0x128>(x);           // row_ror:8
+    else return __shfl_xor(x, 1 << B, 64);
+}
+
+// a <- u a + i v a_partner for every register, partner across lane bit B
+template <int B, bool TAN, typename T, typename C>
+__device__ __forceinline__ void rot_lane(C *v, T t)
+{
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const T pr = lane_partner<B>(v[r].x), pi = lane_partner<B>(v[r].y);
+        if constexpr (TAN) {
+            v[r].x = v[r].x - t * pi;
+            v[r].y = v[r].y + t * pr;
+        } else {
+            v[r].x = t * v[r].x - pi;
+            v[r].y = t * v[r].y + pr;
+        }
+    }
+}
+
+// pair update specialised for u = 1 (TAN) or v = 1
+template <bool TAN, typename T, typename C>
+__device__ __forceinline__ void rot_pair_s(C &a0, C &a1, T t)
+{
+    C b0, b1;
+    if constexpr (TAN) {
+        b0.x = a0.x - t * a1.y;
+        b0.y = a0.y + t * a1.x;
+        b1.x = a1.x - t * a0.y;
+        b1.y = a1.y + t * a0.x;
+    } else {
+        b0.x = t * a0.x - a1.y;
+        b0.y = t * a0.y + a1.x;
+        b1.x = t * a1.x - a0.y;
+        b1.y = t * a1.y + a0.x;
+    }
+    a0 = b0;
+    a1 = b1;
+}
+
+template <bool TAN, int MASK, typename T, typename C>
+__device__ __forceinline__ void rot_regs_s(C *v, T t)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (MASK & (1 << k))
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (!(r & (1 << k))) rot_pair_s<TAN, T, C>(v[r], v[r | (1 << k)], t);
+}
+
+template <bool TAN, int LMASK, typename T, typename C>
+__device__ __forceinline__ void rot_lanes(C *v, T t)
+{
+    if constexpr (LMASK & 1) rot_lane<0, TAN, T, C>(v, t);
+    if constexpr (LMASK & 2) rot_lane<1, TAN, T, C>(v, t);
+    if constexpr (LMASK & 4) rot_lane<2, TAN, T, C>(v, t);
+    if constexpr (LMASK & 8) rot_lane<3, TAN, T, C>(v, t);
+    if constexpr (LMASK & 16) rot_lane<4, TAN, T, C>(v, t);
+    if constexpr (LMASK & 32) rot_lane<5, TAN, T, C>(v, t);
+}
+
+template <typename T, int W, bool LOW>
+struct PassGeom {
+    using C = cplx_t<T>;
+    static constexpr int NT = 64 << W;
+    static constexpr int TB = 10 + W;                        // tile bits
+    static constexpr int CB = LOW ? TB : (sizeof(C) == 8 ? 4 : 3);   // contiguous rows
+    static constexpr int LMASK = LOW ? 63 : (63 & ~((1 << CB) - 1));
+    static constexpr int MW = (1 << W) - 1;
+    // tile offsets of register r for a thread with lane l and wave w
+    static __device__ __forceinline__ int offA(int lw, int r) { return lw | (r << (6 + W)); }
+    static __device__ __forceinline__ int offB(int l, int w, int r)
+    {
+        return l | ((r & MW) << 6) | (w << (6 + W)) | ((r >> W) << (6 + 2 * W));
+    }
+};
+
+template <typename T, int W, bool LOW, bool TAN>
+__global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ insts, int n, int hb,
+                                                  int step, int pre, int post, int n_plaq)
+{
+    using C = cplx_t<T>;
+    using G = PassGeom<T, W, LOW>;
+    constexpr int TB = G::TB, CB = G::CB;
+    __shared__ C buf[W > 0 ? (1 << TB) : 1];
+    __shared__ uint32_t ptab[kPtabWords];
+    __shared__ C ph_pre[kMaxPlaq + 1], ph_post[kMaxPlaq + 1];
+
+    const DevInst in = insts[blockIdx.y];
+    if (in.step0 + step >= in.n_total) return;   // instance already finished (uniform per block)
+    const RotParam<T> rp = ((const RotParam<T> *)in.rot)[in.step0 + step];
+    if ((rp.u == T(1)) != TAN) return;           // the other rotation form has its own launch
+    C *__restrict__ psi = (C *)in.psi;
+    load_tables<T>(in, n_plaq, pre, post, ptab, ph_pre, ph_post);
+    __syncthreads();
+
+    const T tt = TAN ? rp.v : rp.u;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t n_tiles = 1ull << (n - TB);
+    const int lowb = LOW ? 0 : hb - CB;
+    // element offset of a tile's first amplitude, and per-thread / per-register offsets
+    auto tile_base = [&](uint64_t tile) -> uint64_t {
+        if constexpr (LOW) return tile << TB;
+        else return ((tile & ((1ull << lowb) - 1)) << CB) | ((tile >> lowb) << (hb + TB - CB));
+    };
+    // offset of tile offset o inside a tile (tile bits >= CB spread from index bit hb)
+    auto spread = [&](int o) -> uint64_t {
+        if constexpr (LOW) return (uint64_t)o;
+        else return (uint64_t)(o & ((1 << CB) - 1)) | ((uint64_t)(o >> CB) << hb);
+    };
+    auto gbit = [&](int i) -> int { return (LOW || i < CB) ? i : hb + (i - CB); };
+    uint32_t qa[4], qb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        qa[k] = link_set(gbit(6 + W + k), ptab);
+        qb[k] = link_set(gbit(k < W ? 6 + k : 6 + W + k), ptab);
+    }
+    const int lwA = l | (w << 6);
+    const int lwB = l | (w << (6 + W));
+    // per-thread element offsets fit 32 bits (checked by the launcher)
+    const uint32_t thrA = (uint32_t)spread(lwA), thrB = (uint32_t)spread(lwB);
+
+    auto load = [&](uint64_t tile, C *dst) {
+        const C *tp = psi + tile_base(tile);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[r] = (tp + spread(r << (6 + W)))[thrA];
+    };
+
+    uint64_t tile = blockIdx.x;
+    if (tile >= n_tiles) return;
+    C v[16], nv[16];
+    load(tile, v);
+    for (;;) {
+        const uint64_t next = tile + gridDim.x;
+        if (next < n_tiles) load(next, nv);
+        C *tp = psi + tile_base(tile);
+        if (pre >= 0) apply_phase_regs<C, 4>(v, syndrome(tile_base(tile) + thrA, ptab), qa, ph_pre);
+        rot_regs_s<TAN, 15, T, C>(v, tt);
+        rot_lanes<TAN, G::LMASK, T, C>(v, tt);
+        if constexpr (W > 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[G::offA(lwA, r)] = v[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = buf[G::offB(l, w, r)];
+            __syncthreads();
+            rot_regs_s<TAN, (1 << W) - 1, T, C>(v, tt);
+        }
+        if (post >= 0)
+            apply_phase_regs<C, 4>(v, syndrome(tile_base(tile) + (W > 0 ? thrB : thrA), ptab),
+                                   W > 0 ? qb : qa, ph_post);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if constexpr (W > 0) (tp + spread(G::offB(0, 0, r)))[thrB] = v[r];
+            else (tp + spread(r << (6 + W)))[thrA] = v[r];
+        }
+        if (next >= n_tiles) break;
+        tile = next;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = nv[r];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -555,7 +761,8 @@ const char *kernel_family_name(int kf)
 {
     static const char *names[KF_COUNT] = {"init", "pass_low", "pass_high", "phase", "small",
                                           "gate_rx", "gate_rz", "gate_cnot", "reduce_diag",
-                                          "reduce_flip", "reduce_dos", "sample"};
+                                          "reduce_flip", "reduce_dos", "sample", "tile_low",
+                                          "tile_high"};
     return (kf >= 0 && kf < KF_COUNT) ? names[kf] : "?";
 }
 
@@ -592,6 +799,72 @@ hipError_t launch_low(int dtype, const DevInst *dev_inst, int n_inst, int n, int
         hipLaunchKernelGGL(k_low<double>, grid, dim3(kLowThreads), 0, st, dev_inst, step, pre,
                            post, n_plaq);
     return hipGetLastError();
+}
+
+template <typename T, int W, bool LOW>
+static hipError_t launch_pass_t(const DevInst *dev_inst, int n_inst, int n, int hb, int step,
+                                int pre, int post, int n_plaq, int forms, hipStream_t st)
+{
+    constexpr int TB = 10 + W;
+    const uint64_t n_tiles = 1ull << (n - TB);
+    // one resident workgroup per CU for 128 KiB tiles, more for smaller ones
+    const uint64_t per_cu = (W >= 3) ? 1 : (W == 2 ? 2 : 4);
+    uint64_t grid = n_tiles < 256 * per_cu ? n_tiles : 256 * per_cu;
+    if (n_inst > 1) grid = n_tiles < 64 ? n_tiles : 64;
+    const dim3 g((unsigned)grid, (unsigned)n_inst), b(64 << W);
+    if (forms & 1)
+        hipLaunchKernelGGL((k_pass<T, W, LOW, true>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
+    if (forms & 2)
+        hipLaunchKernelGGL((k_pass<T, W, LOW, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
+    return hipGetLastError();
+}
+
+int pass_tile_bits(int dtype, int low, int h)
+{
+    // rotated bits: low tile 10+W; high tile (lanes above the 128-byte row) + 4 + W
+    if (low) return dtype == LGT_C64 ? 14 : 13;
+    const int lane_rot = dtype == LGT_C64 ? 2 : 3;
+    const int w = h - 4 - lane_rot;
+    return (w < 0 || w > 4 || (dtype != LGT_C64 && w > 3)) ? -1 : 10 + w;
+}
+
+bool pass_offsets_fit(int dtype, int n, int low, int hb, int h)
+{
+    // per-thread element offsets of a high tile must stay below 2^32 bytes
+    const int tb = pass_tile_bits(dtype, low, h);
+    if (tb < 0) return false;
+    if (low) return true;
+    const int cb = dtype == LGT_C64 ? 4 : 3, w = tb - 10, eb = dtype == LGT_C64 ? 3 : 4;
+    return hb + (6 + w - cb) + eb <= 32 && hb + h <= n;
+}
+
+hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, int low, int hb,
+                       int h, int step, int pre, int post, int n_plaq, int forms, hipStream_t st)
+{
+    const int tb = pass_tile_bits(dtype, low, h);
+    if (tb < 0 || n < tb || !pass_offsets_fit(dtype, n, low, hb, h)) return hipErrorInvalidValue;
+    const int w = tb - 10;
+    if (!low) {
+        const int cb = dtype == LGT_C64 ? 4 : 3;
+        if (hb < cb) return hipErrorInvalidValue;
+    }
+    if (dtype == LGT_C64) {
+        if (low) return launch_pass_t<float, 4, true>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+        switch (w) {
+        case 0: return launch_pass_t<float, 0, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+        case 1: return launch_pass_t<float, 1, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+        case 2: return launch_pass_t<float, 2, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+        case 3: return launch_pass_t<float, 3, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+        default: return launch_pass_t<float, 4, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+        }
+    }
+    if (low) return launch_pass_t<double, 3, true>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+    switch (w) {
+    case 0: return launch_pass_t<double, 0, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+    case 1: return launch_pass_t<double, 1, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+    case 2: return launch_pass_t<double, 2, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+    default: return launch_pass_t<double, 3, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+    }
 }
 
 template <typename T>

@@ -94,20 +94,26 @@ struct DevInst {
 };
 
 // kernel launch plan for one link layer of an N-link state
+enum PassKind { PASS_LOW12 = 0, PASS_HIGH_REG = 1, PASS_TILE_LOW = 2, PASS_TILE_HIGH = 3 };
+struct Pass {
+    int kind = 0;
+    int q0 = 0;                // first rotated index bit (high passes)
+    int h = 0;                 // rotated bits (high passes)
+};
 struct PassPlan {
     int n_passes = 0;
-    int low_bits = 0;          // first pass: contiguous tile of 2^low_bits amplitudes
-    int hi_q0[8] = {0};        // further passes: qubits [q0, q0+h) from registers
-    int hi_h[8] = {0};
+    Pass pass[8];
 };
-PassPlan plan_passes(int n_links, int dtype);
+// plan = 0: choose (tile passes unless too few tiles or too wide offsets); 1: 12-bit low
+// tile + register passes; 2: tile passes unconditionally
+PassPlan plan_passes(int n_links, int dtype, int plan = 0, int n_inst = 1);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).  All return hipSuccess or the HIP error.
 // ---------------------------------------------------------------------------
 enum KernelFamily {
     KF_INIT = 0, KF_LOW, KF_HIGH, KF_PHASE, KF_SMALL, KF_GATE_RX, KF_GATE_RZ, KF_GATE_CNOT,
-    KF_RED_DIAG, KF_RED_FLIP, KF_RED_DOS, KF_SAMPLE, KF_COUNT
+    KF_RED_DIAG, KF_RED_FLIP, KF_RED_DOS, KF_SAMPLE, KF_TILE_LOW, KF_TILE_HIGH, KF_COUNT
 };
 const char *kernel_family_name(int kf);
 
@@ -119,6 +125,12 @@ hipError_t launch_low(int dtype, const DevInst *dev_inst, int n_inst, int n, int
                       hipStream_t st);
 hipError_t launch_high(int dtype, const DevInst *dev_inst, int n_inst, int n, int q0, int h,
                        int step, int post_phase_idx, int n_plaq, hipStream_t st);
+// persistent tile pass; forms: bit 0 = launch for tan-form steps, bit 1 = cot-form steps
+hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, int low, int hb,
+                       int h, int step, int pre, int post, int n_plaq, int forms, hipStream_t st);
+// tile bits of the persistent pass rotating h bits (low: the whole low tile), -1 if none
+int pass_tile_bits(int dtype, int low, int h);
+bool pass_offsets_fit(int dtype, int n, int low, int hb, int h);
 hipError_t launch_phase(int dtype, const DevInst *dev_inst, int n_inst, int n, int phase_idx,
                         int n_plaq, hipStream_t st);
 // whole evolution of small states (n <= 12) held in LDS, one workgroup per instance
@@ -126,9 +138,10 @@ hipError_t launch_small(int dtype, const DevInst *dev_inst, int n_inst, int n, i
                         int pre_phase, int n_plaq, hipStream_t st);
 // enqueue `count` fused substeps for n_inst instances (api.cpp); pre_first: phase index
 // applied before the first link layer or -1; the phase after layer j is post_off + j
+// forms[j]: bit 0 if some instance's link layer j uses the tan form, bit 1 the cot form
 hipError_t enqueue_fused_steps(int dtype, int n_links, int n_plaq, const DevInst *dev_inst,
                                int n_inst, int count, int pre_first, int post_off,
-                               hipStream_t st, void *prof_ctx);
+                               const uint8_t *forms, hipStream_t st, void *prof_ctx);
 bool small_supported(int dtype, int n);
 // circuit-form gates
 hipError_t launch_gate_rx(int dtype, void *psi, int n, int q, double phi, hipStream_t st);

@@ -64,6 +64,7 @@ struct Run {
     void *tables = nullptr;        // rot | phase
     size_t rot_bytes = 0;
     int n_total = 0, pre = 0, step = 0;
+    std::vector<uint8_t> forms;   // per step: 1 tan-form, 2 cot-form link rotation
     double cx_last = 0, cz_last = 0;
 };
 
@@ -223,6 +224,8 @@ lgt_status admit(lgt_server *s, Run *r)
     }
     r->n_total = st.n_steps;
     r->pre = st.pre_phase;
+    r->forms.resize(st.n_steps);
+    for (int j = 0; j < st.n_steps; ++j) r->forms[j] = (st.rot_u[j] == 1.0) ? 1 : 2;
     r->step = 0;
     if (hipMallocAsync(&r->psi, sr.state_bytes, s->stream) != hipSuccess) return LGT_E_OOM;
     if (hipMallocAsync(&r->tables, blob.size() + 256, s->stream) != hipSuccess) return LGT_E_OOM;
@@ -341,9 +344,13 @@ void worker_loop(lgt_server *s)
             int steps = 0;
             for (Run *r : groups[l.second.first]) steps = std::max(steps, r->n_total - r->step);
             steps = std::min(steps, s->chunk);
+            std::vector<uint8_t> forms(steps, 0);
+            for (Run *r : groups[l.second.first])
+                for (int j = 0; j < steps && r->step + j < r->n_total; ++j) forms[j] |= r->forms[r->step + j];
             if (enqueue_fused_steps(l.second.first.dtype, sr.lat.n_links, sr.lat.n_plaq,
                                     (const DevInst *)((char *)s->inst_dev + l.first),
-                                    l.second.second, steps, -1, 0, s->stream, nullptr) != hipSuccess)
+                                    l.second.second, steps, -1, 0, forms.data(), s->stream,
+                                    nullptr) != hipSuccess)
                 dev_fail = true;
         }
         if (!dev_fail && hipStreamSynchronize(s->stream) != hipSuccess) dev_fail = true;
