@@ -218,14 +218,6 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
     // choice depends on the lattice only, so batched and single runs round identically.
     (void)n_inst;
     if (n_links < low || (1 << (n_links - low)) < 64) plan = 1;
-    if (plan == 0) {
-        PassPlan t = plan_passes(n_links, dtype, 2, n_inst);
-        for (int i = 1; i < t.n_passes; ++i)
-            if (t.pass[i].kind == PASS_TILE_HIGH &&
-                !pass_offsets_fit(dtype, n_links, 0, t.pass[i].q0, t.pass[i].h))
-                plan = 1;
-        if (plan == 0) return t;
-    }
     if (plan == 1) {
         // 12-bit low tile, then register passes of at most 6 (complex64) / 5 bits
         p.pass[p.n_passes++] = Pass{PASS_LOW12, 0, 12};
@@ -239,18 +231,22 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
         }
         return p;
     }
-    // persistent tile passes: one low tile, then high tiles of up to 10 rotated bits;
-    // chunks the tile pass cannot take go to the register pass
-    p.pass[p.n_passes++] = Pass{PASS_TILE_LOW, 0, low};
-    int rest = n_links - low, q = low;
-    const int reg_max = dtype == LGT_C64 ? 6 : 5;
-    while (rest > 0) {
-        int h = rest < 10 ? rest : 10;
-        while (h > reg_max && pass_tile_bits(dtype, 0, h) < 0) --h;
-        const bool tile = pass_tile_bits(dtype, 0, h) >= 0 && h > 4;
-        p.pass[p.n_passes++] = Pass{tile ? PASS_TILE_HIGH : PASS_HIGH_REG, q, h};
+    // persistent tile passes: one low tile, then as few high tiles as possible, each with
+    // the longest rows its width allows; chunks no tile pass takes go to register passes
+    p.pass[p.n_passes++] = Pass{PASS_TILE_LOW, 0, low, 0};
+    const int rest = n_links - low, reg_max = dtype == LGT_C64 ? 6 : 5;
+    const int cb_lo = dtype == LGT_C64 ? 4 : 3;
+    const int nh = (rest + 9) / 10;
+    int q = low;
+    for (int i = 0; i < nh; ++i) {
+        const int h = rest / nh + (i < rest % nh ? 1 : 0);
+        int cb = -1;
+        for (int c = cb_lo + 1; c >= cb_lo && cb < 0; --c)
+            if (pass_wave_bits(dtype, 0, h, c) >= 0 && pass_offsets_fit(dtype, n_links, 0, q, h, c)) cb = c;
+        if (cb >= 0) p.pass[p.n_passes++] = Pass{PASS_TILE_HIGH, q, h, cb};
+        else if (h <= reg_max) p.pass[p.n_passes++] = Pass{PASS_HIGH_REG, q, h, 0};
+        else return plan_passes(n_links, dtype, 1, n_inst);
         q += h;
-        rest -= h;
     }
     return p;
 }
@@ -296,12 +292,12 @@ hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_
                 break;
             case PASS_TILE_LOW:
                 e = run(KF_TILE_LOW, [&] {
-                    return launch_tile(dtype, dev_inst, n_inst, n, 1, 0, 0, j, pre, post, n_plaq, fm, st);
+                    return launch_tile(dtype, dev_inst, n_inst, n, 1, 0, 0, 0, j, pre, post, n_plaq, fm, st);
                 });
                 break;
             case PASS_TILE_HIGH:
                 e = run(KF_TILE_HIGH, [&] {
-                    return launch_tile(dtype, dev_inst, n_inst, n, 0, ps.q0, ps.h, j, pre, post, n_plaq, fm, st);
+                    return launch_tile(dtype, dev_inst, n_inst, n, 0, ps.q0, ps.h, ps.cb, j, pre, post, n_plaq, fm, st);
                 });
                 break;
             default:

@@ -217,19 +217,23 @@ __device__ __forceinline__ T lane_partner(T x)
     else return __shfl_xor(x, 1 << B, 64);
 }
 
-// a <- u a + i v a_partner for every register, partner across lane bit B
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// a <- u a + i v a_partner for every register, partner across lane bit B.  tv / ntv hold
+// t and -t in vector registers, so the cross-lane move can fold into the multiply-add.
 template <int B, bool TAN, typename T, typename C>
-__device__ __forceinline__ void rot_lane(C *v, T t)
+__device__ __forceinline__ void rot_lane(C *v, T tv, T ntv)
 {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const T pr = lane_partner<B>(v[r].x), pi = lane_partner<B>(v[r].y);
         if constexpr (TAN) {
-            v[r].x = v[r].x - t * pi;
-            v[r].y = v[r].y + t * pr;
+            v[r].x = fma_t(ntv, pi, v[r].x);
+            v[r].y = fma_t(tv, pr, v[r].y);
         } else {
-            v[r].x = t * v[r].x - pi;
-            v[r].y = t * v[r].y + pr;
+            v[r].x = fma_t(tv, v[r].x, -pi);
+            v[r].y = fma_t(tv, v[r].y, pr);
         }
     }
 }
@@ -268,20 +272,27 @@ __device__ __forceinline__ void rot_regs_s(C *v, T t)
 template <bool TAN, int LMASK, typename T, typename C>
 __device__ __forceinline__ void rot_lanes(C *v, T t)
 {
-    if constexpr (LMASK & 1) rot_lane<0, TAN, T, C>(v, t);
-    if constexpr (LMASK & 2) rot_lane<1, TAN, T, C>(v, t);
-    if constexpr (LMASK & 4) rot_lane<2, TAN, T, C>(v, t);
-    if constexpr (LMASK & 8) rot_lane<3, TAN, T, C>(v, t);
-    if constexpr (LMASK & 16) rot_lane<4, TAN, T, C>(v, t);
-    if constexpr (LMASK & 32) rot_lane<5, TAN, T, C>(v, t);
+    // keep t and -t in VGPRs (an empty asm hides their uniformity from the compiler)
+    T tv = t, ntv = -t;
+    if constexpr (sizeof(T) == 4) {
+        asm volatile("" : "+v"(tv));
+        asm volatile("" : "+v"(ntv));
+    }
+    if constexpr (LMASK & 1) rot_lane<0, TAN, T, C>(v, tv, ntv);
+    if constexpr (LMASK & 2) rot_lane<1, TAN, T, C>(v, tv, ntv);
+    if constexpr (LMASK & 4) rot_lane<2, TAN, T, C>(v, tv, ntv);
+    if constexpr (LMASK & 8) rot_lane<3, TAN, T, C>(v, tv, ntv);
+    if constexpr (LMASK & 16) rot_lane<4, TAN, T, C>(v, tv, ntv);
+    if constexpr (LMASK & 32) rot_lane<5, TAN, T, C>(v, tv, ntv);
 }
 
-template <typename T, int W, bool LOW>
+template <typename T, int W, int ROWB>
 struct PassGeom {
     using C = cplx_t<T>;
+    static constexpr bool LOW = ROWB >= 10 + W;
     static constexpr int NT = 64 << W;
     static constexpr int TB = 10 + W;                        // tile bits
-    static constexpr int CB = LOW ? TB : (sizeof(C) == 8 ? 4 : 3);   // contiguous rows
+    static constexpr int CB = LOW ? TB : ROWB;               // contiguous row bits
     static constexpr int LMASK = LOW ? 63 : (63 & ~((1 << CB) - 1));
     static constexpr int MW = (1 << W) - 1;
     // tile offsets of register r for a thread with lane l and wave w
@@ -292,12 +303,13 @@ struct PassGeom {
     }
 };
 
-template <typename T, int W, bool LOW, bool TAN>
+template <typename T, int W, int ROWB, bool TAN>
 __global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ insts, int n, int hb,
                                                   int step, int pre, int post, int n_plaq)
 {
     using C = cplx_t<T>;
-    using G = PassGeom<T, W, LOW>;
+    using G = PassGeom<T, W, ROWB>;
+    constexpr bool LOW = G::LOW;
     constexpr int TB = G::TB, CB = G::CB;
     __shared__ C buf[W > 0 ? (1 << TB) : 1];
     __shared__ uint32_t ptab[kPtabWords];
@@ -308,14 +320,11 @@ __global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ in
     const RotParam<T> rp = ((const RotParam<T> *)in.rot)[in.step0 + step];
     if ((rp.u == T(1)) != TAN) return;           // the other rotation form has its own launch
     C *__restrict__ psi = (C *)in.psi;
-    load_tables<T>(in, n_plaq, pre, post, ptab, ph_pre, ph_post);
-    __syncthreads();
-
     const T tt = TAN ? rp.v : rp.u;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t n_tiles = 1ull << (n - TB);
     const int lowb = LOW ? 0 : hb - CB;
-    // element offset of a tile's first amplitude, and per-thread / per-register offsets
+    // element offset of a tile's first amplitude
     auto tile_base = [&](uint64_t tile) -> uint64_t {
         if constexpr (LOW) return tile << TB;
         else return ((tile & ((1ull << lowb) - 1)) << CB) | ((tile >> lowb) << (hb + TB - CB));
@@ -326,27 +335,32 @@ __global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ in
         else return (uint64_t)(o & ((1 << CB) - 1)) | ((uint64_t)(o >> CB) << hb);
     };
     auto gbit = [&](int i) -> int { return (LOW || i < CB) ? i : hb + (i - CB); };
-    uint32_t qa[4], qb[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        qa[k] = link_set(gbit(6 + W + k), ptab);
-        qb[k] = link_set(gbit(k < W ? 6 + k : 6 + W + k), ptab);
-    }
     const int lwA = l | (w << 6);
     const int lwB = l | (w << (6 + W));
     // per-thread element offsets fit 32 bits (checked by the launcher)
     const uint32_t thrA = (uint32_t)spread(lwA), thrB = (uint32_t)spread(lwB);
-
     auto load = [&](uint64_t tile, C *dst) {
         const C *tp = psi + tile_base(tile);
 #pragma unroll
         for (int r = 0; r < 16; ++r) dst[r] = (tp + spread(r << (6 + W)))[thrA];
     };
-
     uint64_t tile = blockIdx.x;
     if (tile >= n_tiles) return;
     C v[16], nv[16];
-    load(tile, v);
+    load(tile, v);   // first tile in flight while the tables are staged
+    // tables are only needed by passes that apply a phase
+    const bool phased = pre >= 0 || post >= 0;
+    uint32_t qa[4] = {0, 0, 0, 0}, qb[4] = {0, 0, 0, 0};
+    if (phased) {
+        load_tables<T>(in, n_plaq, pre, post, ptab, ph_pre, ph_post);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            qa[k] = link_set(gbit(6 + W + k), ptab);
+            qb[k] = link_set(gbit(k < W ? 6 + k : 6 + W + k), ptab);
+        }
+    }
+
     for (;;) {
         const uint64_t next = tile + gridDim.x;
         if (next < n_tiles) load(next, nv);
@@ -801,71 +815,82 @@ hipError_t launch_low(int dtype, const DevInst *dev_inst, int n_inst, int n, int
     return hipGetLastError();
 }
 
-template <typename T, int W, bool LOW>
+template <typename T, int W, int ROWB>
 static hipError_t launch_pass_t(const DevInst *dev_inst, int n_inst, int n, int hb, int step,
                                 int pre, int post, int n_plaq, int forms, hipStream_t st)
 {
     constexpr int TB = 10 + W;
     const uint64_t n_tiles = 1ull << (n - TB);
     // one resident workgroup per CU for 128 KiB tiles, more for smaller ones
+    // resident workgroups per CU: one for 128 KiB tiles, more for smaller ones; a batch
+    // splits the resident slots of the 256 CUs between its instances
     const uint64_t per_cu = (W >= 3) ? 1 : (W == 2 ? 2 : 4);
-    uint64_t grid = n_tiles < 256 * per_cu ? n_tiles : 256 * per_cu;
-    if (n_inst > 1) grid = n_tiles < 64 ? n_tiles : 64;
+    uint64_t slots = 256 * per_cu / (uint64_t)n_inst;
+    if (slots < 1) slots = 1;
+    const uint64_t grid = n_tiles < slots ? n_tiles : slots;
     const dim3 g((unsigned)grid, (unsigned)n_inst), b(64 << W);
     if (forms & 1)
-        hipLaunchKernelGGL((k_pass<T, W, LOW, true>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
+        hipLaunchKernelGGL((k_pass<T, W, ROWB, true>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
     if (forms & 2)
-        hipLaunchKernelGGL((k_pass<T, W, LOW, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
+        hipLaunchKernelGGL((k_pass<T, W, ROWB, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
     return hipGetLastError();
 }
 
-int pass_tile_bits(int dtype, int low, int h)
+int pass_wave_bits(int dtype, int low, int h, int cb)
 {
-    // rotated bits: low tile 10+W; high tile (lanes above the 128-byte row) + 4 + W
-    if (low) return dtype == LGT_C64 ? 14 : 13;
-    const int lane_rot = dtype == LGT_C64 ? 2 : 3;
-    const int w = h - 4 - lane_rot;
-    return (w < 0 || w > 4 || (dtype != LGT_C64 && w > 3)) ? -1 : 10 + w;
+    // low tile: 10+W bits, W = 4 (complex64) / 3 (complex128).  High tile with rows of
+    // 2^cb amplitudes rotates (6-cb) lane bits + 4 register bits + W wave bits.
+    const int wmax = dtype == LGT_C64 ? 4 : 3;
+    if (low) return wmax;
+    const int cb_lo = dtype == LGT_C64 ? 4 : 3;
+    if (cb < cb_lo || cb > cb_lo + 1) return -1;
+    const int w = h - (10 - cb);
+    return (w < 0 || w > wmax) ? -1 : w;
 }
 
-bool pass_offsets_fit(int dtype, int n, int low, int hb, int h)
+bool pass_offsets_fit(int dtype, int n, int low, int hb, int h, int cb)
 {
     // per-thread element offsets of a high tile must stay below 2^32 bytes
-    const int tb = pass_tile_bits(dtype, low, h);
-    if (tb < 0) return false;
-    if (low) return true;
-    const int cb = dtype == LGT_C64 ? 4 : 3, w = tb - 10, eb = dtype == LGT_C64 ? 3 : 4;
-    return hb + (6 + w - cb) + eb <= 32 && hb + h <= n;
+    const int w = pass_wave_bits(dtype, low, h, cb);
+    if (w < 0) return false;
+    if (low) return n >= 10 + w;
+    const int eb = dtype == LGT_C64 ? 3 : 4;
+    return hb >= cb && hb + h <= n && hb + (6 + w - cb) + eb <= 32;
 }
 
+#define LGT_PASS_CASES(T, CB)                                                                   \
+    switch (w) {                                                                                \
+    case 0: return launch_pass_t<T, 0, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st); \
+    case 1: return launch_pass_t<T, 1, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st); \
+    case 2: return launch_pass_t<T, 2, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st); \
+    case 3: return launch_pass_t<T, 3, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st); \
+    default: break;                                                                             \
+    }
+
 hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, int low, int hb,
-                       int h, int step, int pre, int post, int n_plaq, int forms, hipStream_t st)
+                       int h, int cb, int step, int pre, int post, int n_plaq, int forms,
+                       hipStream_t st)
 {
-    const int tb = pass_tile_bits(dtype, low, h);
-    if (tb < 0 || n < tb || !pass_offsets_fit(dtype, n, low, hb, h)) return hipErrorInvalidValue;
-    const int w = tb - 10;
-    if (!low) {
-        const int cb = dtype == LGT_C64 ? 4 : 3;
-        if (hb < cb) return hipErrorInvalidValue;
-    }
+    if (!pass_offsets_fit(dtype, n, low, hb, h, cb)) return hipErrorInvalidValue;
+    const int w = pass_wave_bits(dtype, low, h, cb);
     if (dtype == LGT_C64) {
-        if (low) return launch_pass_t<float, 4, true>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
-        switch (w) {
-        case 0: return launch_pass_t<float, 0, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
-        case 1: return launch_pass_t<float, 1, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
-        case 2: return launch_pass_t<float, 2, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
-        case 3: return launch_pass_t<float, 3, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
-        default: return launch_pass_t<float, 4, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+        if (low) return launch_pass_t<float, 4, 14>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+        if (cb == 4) {
+            LGT_PASS_CASES(float, 4)
+            return launch_pass_t<float, 4, 4>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
         }
+        LGT_PASS_CASES(float, 5)
+        return launch_pass_t<float, 4, 5>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
     }
-    if (low) return launch_pass_t<double, 3, true>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
-    switch (w) {
-    case 0: return launch_pass_t<double, 0, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
-    case 1: return launch_pass_t<double, 1, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
-    case 2: return launch_pass_t<double, 2, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
-    default: return launch_pass_t<double, 3, false>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+    if (low) return launch_pass_t<double, 3, 13>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+    if (cb == 3) {
+        LGT_PASS_CASES(double, 3)
+    } else {
+        LGT_PASS_CASES(double, 4)
     }
+    return hipErrorInvalidValue;
 }
+#undef LGT_PASS_CASES
 
 template <typename T>
 static hipError_t launch_high_t(const DevInst *dev_inst, int n_inst, int n, int q0, int h,

@@ -99,6 +99,7 @@ struct Pass {
     int kind = 0;
     int q0 = 0;                // first rotated index bit (high passes)
     int h = 0;                 // rotated bits (high passes)
+    int cb = 0;                // contiguous row bits (tile high passes)
 };
 struct PassPlan {
     int n_passes = 0;
@@ -125,12 +126,15 @@ hipError_t launch_low(int dtype, const DevInst *dev_inst, int n_inst, int n, int
                       hipStream_t st);
 hipError_t launch_high(int dtype, const DevInst *dev_inst, int n_inst, int n, int q0, int h,
                        int step, int post_phase_idx, int n_plaq, hipStream_t st);
-// persistent tile pass; forms: bit 0 = launch for tan-form steps, bit 1 = cot-form steps
+// persistent tile pass; forms: bit 0 = launch for tan-form steps, bit 1 = cot-form steps.
+// High passes keep rows of 2^cb amplitudes contiguous (cb = 4 or 5 for complex64,
+// 3 or 4 for complex128) and rotate index bits [hb, hb+h).
 hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, int low, int hb,
-                       int h, int step, int pre, int post, int n_plaq, int forms, hipStream_t st);
-// tile bits of the persistent pass rotating h bits (low: the whole low tile), -1 if none
-int pass_tile_bits(int dtype, int low, int h);
-bool pass_offsets_fit(int dtype, int n, int low, int hb, int h);
+                       int h, int cb, int step, int pre, int post, int n_plaq, int forms,
+                       hipStream_t st);
+// wave bits of the tile pass rotating h bits with rows of 2^cb, -1 if no such pass
+int pass_wave_bits(int dtype, int low, int h, int cb);
+bool pass_offsets_fit(int dtype, int n, int low, int hb, int h, int cb);
 hipError_t launch_phase(int dtype, const DevInst *dev_inst, int n_inst, int n, int phase_idx,
                         int n_plaq, hipStream_t st);
 // whole evolution of small states (n <= 12) held in LDS, one workgroup per instance
