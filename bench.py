@@ -66,7 +66,8 @@ def run_job(lgt, ctx, w, masks, stars_n, plaq_n):
 def roofline_from_stats(stats, state_bytes, traffic):
     """Dominant pass kernel: algorithmic bytes (one read + one write of the state per
     launch) over its mean HIP-event duration."""
-    passes = {k: v for k, v in stats.items() if k in ("pass_low", "pass_high", "small")}
+    passes = {k: v for k, v in stats.items()
+              if k in ("tile_low", "tile_high", "pass_low", "pass_high", "small")}
     if not passes:
         return None
     name, (launches, total_ms) = max(passes.items(), key=lambda kv: kv[1][1])
@@ -164,21 +165,71 @@ def serving(lgt, n_requests, rate):
             "mix": "60% 3x3, 30% 2x2x2, 10% 2x2; lambda U[0,2]; steps U{500..4000}; order 1|2"}
 
 
-def cpu_baseline(n_steps=2):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+def cpu_baseline(target_s=12.0, max_steps=200):
+    """The oracle, as it stands, on a bounded sample of the same workload: symmetric
+    Trotter steps of the 2x2x2 run at the first coupling, repeated until about
+    target_s seconds of host time have been spent."""
     import oracle
     lat = oracle.Lattice(3, (2, 2, 2))
     w = workloads.CONFIG3
     dt, cx, cz = oracle.schedule_plaquette_ramp(w.T, w.n_steps, w.lambdas[0], 1.0)
     psi = oracle.plus_state(lat.N)
-    t0 = time.perf_counter()
-    oracle.evolve(psi, lat, dt, cx[:n_steps], cz[:n_steps], w.order)
-    el = time.perf_counter() - t0
-    upd = n_steps * (1 << lat.N) * (lat.N + 1)
+    done, el = 0, 0.0
+    while el < target_s and done < max_steps:
+        t0 = time.perf_counter()
+        oracle.evolve(psi, lat, dt, cx[done:done + 1], cz[done:done + 1], w.order)
+        el += time.perf_counter() - t0
+        done += 1
+    upd = done * (1 << lat.N) * (lat.N + 1)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": upd / el, "unit": "amp-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_steps} symmetric Trotter steps of the 2x2x2 (24-link) run at "
-                      f"lambda={w.lambdas[0]}, complex128 oracle, {el:.1f} s"}
+            "sample": f"{done} symmetric Trotter steps (of 2000) of the 2x2x2 (24-link) run at "
+                      f"lambda={w.lambdas[0]}, complex128 oracle, OpenMP loops, {el:.1f} s"}
+
+
+def variants(lgt):
+    """Per-Trotter-step time of the other precisions, forms and sizes (secondary)."""
+    out = {}
+
+    def per_step(d, L, dtype, n, form=0, order=2):
+        ctx = lgt.lgt_create(d, list(L), 1, dtype)
+        try:
+            s = lgt.make_schedule(0.05 * n, n, 1.0, 1.0)
+            lgt.lgt_evolve(ctx, s, order, form, 0, min(n, 2))
+            lgt.lgt_sync(ctx)
+            t0 = time.perf_counter()
+            lgt.lgt_evolve(ctx, s, order, form, 0, n)
+            lgt.lgt_sync(ctx)
+            el = (time.perf_counter() - t0) / n
+            sb = lgt.lgt_info(ctx)["state_bytes"]
+        finally:
+            lgt.lgt_destroy(ctx)
+        return {"us_per_trotter_step": el * 1e6,
+                "algorithmic_GBps": 2 * sb / el / 1e9,
+                "algorithmic_hbm_frac": 2 * sb / el / 1e9 / HBM_PEAK_GBS}
+
+    out["2x2x2_c128_fused"] = per_step(3, (2, 2, 2), lgt.LGT_C128, 200)
+    out["2x2x2_c64_circuit"] = per_step(3, (2, 2, 2), lgt.LGT_C64, 4, form=1)
+    out["2x2x2_c128_circuit"] = per_step(3, (2, 2, 2), lgt.LGT_C128, 2, form=1)
+    out["4x4_c64_fused_32links"] = per_step(2, (4, 4), lgt.LGT_C64, 8)
+    out["4x4_c128_fused_32links"] = per_step(2, (4, 4), lgt.LGT_C128, 4)
+    out["3x3_c64_fused_single"] = per_step(2, (3, 3), lgt.LGT_C64, 2000)
+    # the whole 2x2 first-order run (1000 steps, complex128), on chip in one launch
+    w = workloads.CONFIG1
+    ctx = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C128)
+    try:
+        s = lgt.make_schedule(w.T, w.n_steps, 1.0, 1.0)
+        lgt.lgt_evolve(ctx, s, w.order, 0, 0, w.n_steps)
+        lgt.lgt_sync(ctx)
+        lgt.lgt_reset(ctx, lgt.LGT_INIT_PLUS, 0)
+        t0 = time.perf_counter()
+        lgt.lgt_evolve(ctx, s, w.order, 0, 0, w.n_steps)
+        e = lgt.lgt_measure(ctx, lgt.LGT_OBS_ENERGY, cx=1.0, cz=1.0)[0]
+        out["2x2_c128_full_run_ms"] = (time.perf_counter() - t0) * 1e3
+        out["2x2_c128_final_energy"] = e
+    finally:
+        lgt.lgt_destroy(ctx)
+    return out
 
 
 def main():
@@ -190,6 +241,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="profiling runs only: Trotter steps per lambda instead of the full "
+                         "schedule, plus one device-to-device copy of the state (a copy of "
+                         "known size for counter calibration); prints no benchmark line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs one state per GPU; only --gpus 1 is "
@@ -200,6 +255,18 @@ def main():
     w = workloads.CONFIG3
     ctx = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64)
     info = lgt.lgt_info(ctx)
+    if args.profile_steps > 0:
+        other = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64)
+        for lam in w.lambdas[:1]:
+            s = lgt.make_schedule(w.T, w.n_steps, lam, 1.0)
+            lgt.lgt_evolve(ctx, s, w.order, lgt.LGT_FORM_FUSED, 0, args.profile_steps)
+        lgt.lgt_copy_state(other, ctx)
+        lgt.lgt_sync(other)
+        print(json.dumps({"profile_steps": args.profile_steps,
+                          "copy_bytes": info["state_bytes"]}), flush=True)
+        lgt.lgt_destroy(other)
+        lgt.lgt_destroy(ctx)
+        return
     n_links, n_plaq, n_sites = info["n_links"], info["n_plaq"], info["n_sites"]
     masks = [int(m) for m in info["plaq_masks"][:4]] + [lgt.lgt_line_mask(ctx, 0, mu)
                                                         for mu in range(3)]
@@ -245,6 +312,7 @@ def main():
     if not args.no_extras:
         line["lambda_scan"] = lambda_scan(lgt)
         line["serving"] = serving(lgt, args.serve_requests, args.serve_rate)
+        line["variants"] = variants(lgt)
     print(json.dumps(line), flush=True)
 
 

@@ -223,6 +223,14 @@ lgt_status lgt_sample(lgt_ctx *ctx, uint64_t n_shots, uint64_t seed, uint64_t *o
 lgt_status lgt_get_state(lgt_ctx *ctx, void *host, size_t bytes);
 lgt_status lgt_set_state(lgt_ctx *ctx, const void *host, size_t bytes);
 
+/*
+ * lgt_copy_state: device-to-device copy of src's amplitudes into dst (same lattice and
+ * dtype), enqueued on dst's stream after src's stream has drained.  An on-device
+ * checkpoint of a run that is paused between steps (the paper pauses after every step
+ * to measure, Sec. 2.2).
+ */
+lgt_status lgt_copy_state(lgt_ctx *dst, lgt_ctx *src);
+
 /* lgt_sync: wait for the context's stream. */
 lgt_status lgt_sync(lgt_ctx *ctx);
 

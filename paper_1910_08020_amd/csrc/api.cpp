@@ -775,6 +775,20 @@ lgt_status lgt_set_state(lgt_ctx *c, const void *host, size_t bytes)
     return LGT_OK;
 }
 
+lgt_status lgt_copy_state(lgt_ctx *dst, lgt_ctx *src)
+{
+    lgt_status s = check_ctx(dst);
+    if (s) return s;
+    if (!src || src->dtype != dst->dtype || src->lat.d != dst->lat.d ||
+        std::memcmp(src->lat.L, dst->lat.L, sizeof src->lat.L) != 0 || src->device != dst->device)
+        return fail(dst, LGT_E_INVALID, "copy needs contexts of one lattice, dtype and device");
+    if (src == dst) return LGT_OK;
+    HIPCHK(dst, hipStreamSynchronize(src->stream));
+    HIPCHK(dst, hipMemcpyAsync(dst->state, src->state, dst->state_bytes, hipMemcpyDeviceToDevice,
+                               dst->stream));
+    return LGT_OK;
+}
+
 lgt_status lgt_sync(lgt_ctx *c)
 {
     lgt_status s = check_ctx(c);

@@ -80,6 +80,7 @@ _SIGNATURES = [
     ("lgt_sample", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
     ("lgt_get_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
     ("lgt_set_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
+    ("lgt_copy_state", ctypes.c_int, [_VP, _VP]),
     ("lgt_sync", ctypes.c_int, [_VP]),
     ("lgt_set_profiling", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lgt_kernel_stats", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64), _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
@@ -237,6 +238,10 @@ def lgt_get_state(ctx, nbytes, dtype) -> np.ndarray:
 def lgt_set_state(ctx, arr: np.ndarray):
     arr = np.ascontiguousarray(arr)
     _check(lib().lgt_set_state(ctx, arr.ctypes.data_as(_VP), arr.nbytes), ctx)
+
+
+def lgt_copy_state(dst, src):
+    _check(lib().lgt_copy_state(dst, src), dst)
 
 
 def lgt_sync(ctx):
