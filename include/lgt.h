@@ -235,9 +235,10 @@ lgt_status lgt_copy_state(lgt_ctx *dst, lgt_ctx *src);
 lgt_status lgt_sync(lgt_ctx *ctx);
 
 /*
- * lgt_kernel_stats: per kernel family, the number of launches and the summed
- * duration measured with HIP events on the context's stream, collected while
- * profiling is on (lgt_set_profiling).  names[i] points to a static string.
+ * lgt_set_profiling: on = 0 stops profiling; on = k >= 1 brackets every k-th launch of
+ * each kernel family with HIP events on the context's stream (k = 1: every launch).
+ * lgt_kernel_stats: per kernel family, the number of timed launches and their summed
+ * duration, collected while profiling is on.  names[i] points to a static string.
  * Returns the number of families written (<= cap) in *n.
  */
 lgt_status lgt_set_profiling(lgt_ctx *ctx, int on);

@@ -51,6 +51,8 @@ struct lgt_ctx {
     std::vector<double> partials_host;
     // profiling
     bool profiling = false;
+    int prof_stride = 1;
+    int64_t prof_seen[KF_COUNT] = {0};
     std::vector<ProfEvent> pending;
     std::vector<hipEvent_t> pool;
     int64_t prof_launches[KF_COUNT] = {0};
@@ -151,6 +153,7 @@ template <typename F>
 hipError_t timed(lgt_ctx *c, int kf, F &&launch)
 {
     if (!c->profiling) return launch();
+    if (c->prof_seen[kf]++ % c->prof_stride) return launch();
     ProfEvent pe;
     hipError_t e = prof_begin(c, kf, pe);
     if (e != hipSuccess) return e;
@@ -802,10 +805,12 @@ lgt_status lgt_set_profiling(lgt_ctx *c, int on)
     lgt_status s = check_ctx(c);
     if (s) return s;
     HIPCHK(c, prof_harvest(c));
-    c->profiling = on != 0;
+    c->profiling = on > 0;
+    c->prof_stride = on > 1 ? on : 1;
     for (int k = 0; k < KF_COUNT; ++k) {
         c->prof_launches[k] = 0;
         c->prof_ms[k] = 0;
+        c->prof_seen[k] = 0;
     }
     return LGT_OK;
 }

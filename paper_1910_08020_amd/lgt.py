@@ -248,8 +248,9 @@ def lgt_sync(ctx):
     _check(lib().lgt_sync(ctx), ctx)
 
 
-def lgt_set_profiling(ctx, on: bool):
-    _check(lib().lgt_set_profiling(ctx, 1 if on else 0), ctx)
+def lgt_set_profiling(ctx, on):
+    """on: False/0 off, True/1 every launch, k > 1 every k-th launch per kernel family."""
+    _check(lib().lgt_set_profiling(ctx, int(on)), ctx)
 
 
 def lgt_kernel_stats(ctx) -> dict:
