@@ -245,6 +245,20 @@ lgt_status lgt_set_profiling(lgt_ctx *ctx, int on);
 lgt_status lgt_kernel_stats(lgt_ctx *ctx, const char **names, int64_t *launches,
                             double *total_ms, int cap, int *n);
 
+/*
+ * lgt_tune: autotuner for the link-layer pass plan of this context's lattice and dtype.
+ * Times each candidate plan (12-bit low tile + register passes; LDS tile passes with the
+ * longest or the shortest contiguous rows) over `steps` identity steps on the context's
+ * own state (u = 1, v = 0 and unit phases, which leave every amplitude bit-for-bit
+ * unchanged) and keeps the fastest for later evolve calls on this context.  Plans apply
+ * the same rotations in a different order, so a tuned context may round differently
+ * from an untuned one (within the precision of the dtype).  States of <= 12 links have
+ * a single on-chip kernel and nothing to tune.  1 <= steps <= 1024.
+ * lgt_plan_describe: the plan evolve will use, as text (e.g. "tile_low14 | tile_high(...)").
+ */
+lgt_status lgt_tune(lgt_ctx *ctx, int steps);
+lgt_status lgt_plan_describe(const lgt_ctx *ctx, char *out, size_t len);
+
 /* Message for the last failure on ctx (ctx may be NULL for create/batch calls). */
 const char *lgt_last_error(const lgt_ctx *ctx);
 

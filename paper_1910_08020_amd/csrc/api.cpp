@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -57,6 +58,7 @@ struct lgt_ctx {
     std::vector<hipEvent_t> pool;
     int64_t prof_launches[KF_COUNT] = {0};
     double prof_ms[KF_COUNT] = {0};
+    int plan = 0;   // pass plan code (plan_passes), 0 = built-in rule
     std::string err;
 };
 
@@ -220,7 +222,9 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
     // too few low tiles to fill the GPU: the 12-bit plan gives 4x more workgroups.  The
     // choice depends on the lattice only, so batched and single runs round identically.
     (void)n_inst;
-    if (n_links < low || (1 << (n_links - low)) < 64) plan = 1;
+    if (n_links < low) plan = 1;
+    if (plan == 0 && (1 << (n_links - low)) < 64) plan = 1;
+    const bool long_rows = plan != 3;
     if (plan == 1) {
         // 12-bit low tile, then register passes of at most 6 (complex64) / 5 bits
         p.pass[p.n_passes++] = Pass{PASS_LOW12, 0, 12};
@@ -244,8 +248,10 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
     for (int i = 0; i < nh; ++i) {
         const int h = rest / nh + (i < rest % nh ? 1 : 0);
         int cb = -1;
-        for (int c = cb_lo + 1; c >= cb_lo && cb < 0; --c)
+        for (int k = 0; k < 2 && cb < 0; ++k) {
+            const int c = long_rows ? cb_lo + 1 - k : cb_lo + k;
             if (pass_wave_bits(dtype, 0, h, c) >= 0 && pass_offsets_fit(dtype, n_links, 0, q, h, c)) cb = c;
+        }
         if (cb >= 0) p.pass[p.n_passes++] = Pass{PASS_TILE_HIGH, q, h, cb};
         else if (h <= reg_max) p.pass[p.n_passes++] = Pass{PASS_HIGH_REG, q, h, 0};
         else return plan_passes(n_links, dtype, 1, n_inst);
@@ -259,9 +265,29 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
 namespace lgt {
 
 // enqueue `count` fused substeps of n_inst instances whose pointers sit in dev_inst
+std::string describe_plan(const PassPlan &p, int n_links)
+{
+    if (p.n_passes == 0) return "small(" + std::to_string(n_links) + " links on chip)";
+    std::string s;
+    for (int i = 0; i < p.n_passes; ++i) {
+        const Pass &ps = p.pass[i];
+        if (i) s += " | ";
+        switch (ps.kind) {
+        case PASS_LOW12: s += "low12"; break;
+        case PASS_TILE_LOW: s += "tile_low" + std::to_string(ps.h); break;
+        case PASS_TILE_HIGH:
+            s += "tile_high(q" + std::to_string(ps.q0) + ",h" + std::to_string(ps.h) + ",rows" +
+                 std::to_string(1 << ps.cb) + ")";
+            break;
+        default: s += "reg_high(q" + std::to_string(ps.q0) + ",h" + std::to_string(ps.h) + ")";
+        }
+    }
+    return s;
+}
+
 hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_inst, int n_inst,
                                int count, int pre_first, int post_off, const uint8_t *forms,
-                               hipStream_t st, void *prof_ctx)
+                               int plan_sel, hipStream_t st, void *prof_ctx)
 {
     lgt_ctx *pc = (lgt_ctx *)prof_ctx;
     auto run = [&](int kf, auto &&launch) -> hipError_t {
@@ -274,10 +300,6 @@ hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_
             return launch_small(dtype, dev_inst, n_inst, n, count, pre_first >= 0 ? 1 : 0, n_plaq, st);
         });
     }
-    static const int plan_sel = [] {
-        const char *e = std::getenv("LGT_PASS_PLAN");
-        return e ? std::atoi(e) : 0;
-    }();
     const PassPlan plan = plan_passes(n, dtype, plan_sel, n_inst);
     for (int j = 0; j < count; ++j) {
         const int fm = forms ? (forms[j] ? forms[j] : 1) : 3;
@@ -321,7 +343,7 @@ static hipError_t enqueue_fused(lgt_ctx *c, const DevInst *dev_inst, int n_inst,
                                 int pre_phase, const uint8_t *forms)
 {
     return enqueue_fused_steps(c->dtype, c->lat.n_links, c->lat.n_plaq, dev_inst, n_inst, count,
-                               pre_phase ? 0 : -1, pre_phase, forms, c->stream, c);
+                               pre_phase ? 0 : -1, pre_phase, forms, c->plan, c->stream, c);
 }
 
 // bit 0: tan form (u == 1) of the factored link rotation, bit 1: cot form
@@ -374,6 +396,7 @@ static lgt_status create_common(int d, const int *L, int periodic, lgt_dtype dty
         c->own_stream = true;
     }
     build_parity_tables(c->lat, c->ptab);
+    if (const char *e = std::getenv("LGT_PASS_PLAN")) c->plan = std::atoi(e);   // debugging override
     lgt_ctx *raw = c.get();
     auto bail = [&](const char *m) {
         lgt_destroy(c.release());
@@ -837,6 +860,87 @@ lgt_status lgt_kernel_stats(lgt_ctx *c, const char **names, int64_t *launches, d
 const char *lgt_last_error(const lgt_ctx *c)
 {
     return c ? c->err.c_str() : g_err.c_str();
+}
+
+lgt_status lgt_plan_describe(const lgt_ctx *c, char *out, size_t len)
+{
+    if (!c || !out || len == 0) return fail(nullptr, LGT_E_INVALID, "null argument");
+    const std::string d = describe_plan(plan_passes(c->lat.n_links, c->dtype, c->plan, 1), c->lat.n_links);
+    std::snprintf(out, len, "%s", d.c_str());
+    return d.size() < len ? LGT_OK : fail(const_cast<lgt_ctx *>(c), LGT_E_INVALID, "buffer too short");
+}
+
+lgt_status lgt_tune(lgt_ctx *c, int steps)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (steps < 1 || steps > 1024) return fail(c, LGT_E_INVALID, "steps must be in [1, 1024]");
+    const Lattice &lat = c->lat;
+    const int n = lat.n_links;
+    if (small_supported(c->dtype, n)) return LGT_OK;   // one on-chip kernel: nothing to choose
+    // identity tables: u = 1, v = 0 and unit phases leave every amplitude bit for bit unchanged
+    const int np1 = lat.n_plaq + 1, total = steps + 2;
+    const size_t eb = elem_bytes(c->dtype);
+    std::vector<char> rot((size_t)total * eb, 0), ph((size_t)total * np1 * eb, 0);
+    for (int j = 0; j < total; ++j) {
+        if (c->dtype == LGT_C64) ((float *)rot.data())[2 * j] = 1.0f;
+        else ((double *)rot.data())[2 * j] = 1.0;
+    }
+    for (int k = 0; k < total * np1; ++k) {
+        if (c->dtype == LGT_C64) ((float *)ph.data())[2 * k] = 1.0f;
+        else ((double *)ph.data())[2 * k] = 1.0;
+    }
+    void *drot = nullptr, *dph = nullptr;
+    DevInst *dinst = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&] {
+        if (drot) (void)hipFree(drot);
+        if (dph) (void)hipFree(dph);
+        if (dinst) (void)hipFree(dinst);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    DevInst di{};
+    hipError_t e = hipMalloc(&drot, rot.size());
+    if (e == hipSuccess) e = hipMalloc(&dph, ph.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&dinst, sizeof(DevInst));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemcpyAsync(drot, rot.data(), rot.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dph, ph.data(), ph.size(), hipMemcpyHostToDevice, c->stream);
+    di.psi = c->state;
+    di.rot = drot;
+    di.phase = dph;
+    di.ptab = c->ptab_dev;
+    di.n_total = total;
+    if (e == hipSuccess) e = hipMemcpyAsync(dinst, &di, sizeof di, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    std::vector<uint8_t> forms(total, 1);
+    int best = c->plan;
+    float best_ms = 1e30f;
+    std::vector<std::string> seen;
+    for (int cand : {1, 2, 3}) {
+        if (e != hipSuccess) break;
+        const std::string d = describe_plan(plan_passes(n, c->dtype, cand, 1), n);
+        if (std::find(seen.begin(), seen.end(), d) != seen.end()) continue;
+        seen.push_back(d);
+        e = enqueue_fused_steps(c->dtype, n, lat.n_plaq, dinst, 1, 2, -1, 0, forms.data(), cand, c->stream, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        if (e == hipSuccess)
+            e = enqueue_fused_steps(c->dtype, n, lat.n_plaq, dinst, 1, steps, -1, 0, forms.data(), cand, c->stream, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = cand;
+        }
+    }
+    cleanup();
+    if (e != hipSuccess) return fail(c, LGT_E_DEVICE, std::string("tune: ") + hipGetErrorString(e));
+    c->plan = best;
+    return LGT_OK;
 }
 
 lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule *scheds,

@@ -519,6 +519,85 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(const DevInst *__restri
 }
 
 // ---------------------------------------------------------------------------
+// wave-resident states (6 + RB <= 8 links): one wavefront per instance holds the whole
+// state, lanes on index bits 0..5 and 2^RB registers on bits 6..5+RB, for every step
+// of the call; rotations across lanes and registers, no LDS traffic but the phase table
+// ---------------------------------------------------------------------------
+template <int B, bool TAN, int R, typename T, typename C>
+__device__ __forceinline__ void rot_lane_r(C *v, T t)
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const T pr = lane_partner<B>(v[r].x), pi = lane_partner<B>(v[r].y);
+        if constexpr (TAN) {
+            v[r].x = v[r].x - t * pi;
+            v[r].y = v[r].y + t * pr;
+        } else {
+            v[r].x = t * v[r].x - pi;
+            v[r].y = t * v[r].y + pr;
+        }
+    }
+}
+
+template <bool TAN, int RB, typename T, typename C>
+__device__ __forceinline__ void wave_layer(C *v, T t)
+{
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+#pragma unroll
+        for (int r = 0; r < (1 << RB); ++r)
+            if (!(r & (1 << k))) rot_pair_s<TAN, T, C>(v[r], v[r | (1 << k)], t);
+    rot_lane_r<0, TAN, 1 << RB, T, C>(v, t);
+    rot_lane_r<1, TAN, 1 << RB, T, C>(v, t);
+    rot_lane_r<2, TAN, 1 << RB, T, C>(v, t);
+    rot_lane_r<3, TAN, 1 << RB, T, C>(v, t);
+    rot_lane_r<4, TAN, 1 << RB, T, C>(v, t);
+    rot_lane_r<5, TAN, 1 << RB, T, C>(v, t);
+}
+
+template <typename T, int RB>
+__global__ __launch_bounds__(64) void k_wave(const DevInst *__restrict__ insts, int n_steps,
+                                             int pre, int n_plaq)
+{
+    using C = cplx_t<T>;
+    constexpr int R = 1 << RB;
+    __shared__ uint32_t ptab[kPtabWords];
+    __shared__ C ph[kMaxPlaq + 1];
+    const DevInst in = insts[blockIdx.x];
+    C *__restrict__ psi = (C *)in.psi;
+    const int l = threadIdx.x, np1 = n_plaq + 1;
+    const C *phase = (const C *)in.phase;
+    const RotParam<T> *rot = (const RotParam<T> *)in.rot;
+    for (int i = l; i < kPtabWords; i += 64) ptab[i] = in.ptab[i];
+    __syncthreads();
+    C v[R];
+    int m[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        v[r] = psi[l | (r << 6)];
+        m[r] = __popc(syndrome((uint64_t)(l | (r << 6)), ptab));
+    }
+    auto phase_step = [&](int k) {
+        if (l < np1) ph[l] = phase[(size_t)k * np1 + l];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = cmul(v[r], ph[m[r]]);
+        __syncthreads();
+    };
+    int k = in.ph0;
+    const int steps = min(n_steps, in.n_total - in.step0);
+    if (pre) phase_step(k++);
+    for (int j = 0; j < steps; ++j, ++k) {
+        const RotParam<T> rp = rot[in.step0 + j];
+        if (rp.u == T(1)) wave_layer<true, RB, T, C>(v, rp.v);
+        else wave_layer<false, RB, T, C>(v, rp.u);
+        phase_step(k);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) psi[l | (r << 6)] = v[r];
+}
+
+// ---------------------------------------------------------------------------
 // state preparation
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -933,12 +1012,23 @@ hipError_t launch_phase(int dtype, const DevInst *dev_inst, int n_inst, int n, i
     return hipGetLastError();
 }
 
-bool small_supported(int dtype, int n) { (void)dtype; return n >= 1 && n <= 12; }
+bool small_supported(int dtype, int n) { (void)dtype; return n >= 6 && n <= 12; }
 
 hipError_t launch_small(int dtype, const DevInst *dev_inst, int n_inst, int n, int n_steps,
                         int pre, int n_plaq, hipStream_t st)
 {
     if (!small_supported(dtype, n)) return hipErrorInvalidValue;
+    if (n <= 8) {
+        // the whole state in one wavefront's registers
+#define LGT_WAVE(T, RB) hipLaunchKernelGGL((k_wave<T, RB>), dim3(n_inst), dim3(64), 0, st, dev_inst, n_steps, pre, n_plaq)
+        if (dtype == LGT_C64) {
+            if (n == 6) LGT_WAVE(float, 0); else if (n == 7) LGT_WAVE(float, 1); else LGT_WAVE(float, 2);
+        } else {
+            if (n == 6) LGT_WAVE(double, 0); else if (n == 7) LGT_WAVE(double, 1); else LGT_WAVE(double, 2);
+        }
+#undef LGT_WAVE
+        return hipGetLastError();
+    }
     if (dtype == LGT_C64)
         hipLaunchKernelGGL(k_small<float>, dim3(n_inst), dim3(kSmallThreads), 0, st, dev_inst, n,
                            n_steps, pre, n_plaq);

@@ -105,9 +105,10 @@ struct PassPlan {
     int n_passes = 0;
     Pass pass[8];
 };
-// plan = 0: choose (tile passes unless too few tiles or too wide offsets); 1: 12-bit low
-// tile + register passes; 2: tile passes unconditionally
+// plan = 0: built-in rule (tile passes unless there are too few tiles); 1: 12-bit low
+// tile + register passes; 2: tile passes, longest rows; 3: tile passes, shortest rows
 PassPlan plan_passes(int n_links, int dtype, int plan = 0, int n_inst = 1);
+std::string describe_plan(const PassPlan &p, int n_links);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).  All return hipSuccess or the HIP error.
@@ -137,7 +138,8 @@ int pass_wave_bits(int dtype, int low, int h, int cb);
 bool pass_offsets_fit(int dtype, int n, int low, int hb, int h, int cb);
 hipError_t launch_phase(int dtype, const DevInst *dev_inst, int n_inst, int n, int phase_idx,
                         int n_plaq, hipStream_t st);
-// whole evolution of small states (n <= 12) held in LDS, one workgroup per instance
+// whole evolution of small states, one workgroup per instance: n <= 8 in one wavefront's
+// registers, 9 <= n <= 12 in LDS
 hipError_t launch_small(int dtype, const DevInst *dev_inst, int n_inst, int n, int n_steps,
                         int pre_phase, int n_plaq, hipStream_t st);
 // enqueue `count` fused substeps for n_inst instances (api.cpp); pre_first: phase index
@@ -145,7 +147,7 @@ hipError_t launch_small(int dtype, const DevInst *dev_inst, int n_inst, int n, i
 // forms[j]: bit 0 if some instance's link layer j uses the tan form, bit 1 the cot form
 hipError_t enqueue_fused_steps(int dtype, int n_links, int n_plaq, const DevInst *dev_inst,
                                int n_inst, int count, int pre_first, int post_off,
-                               const uint8_t *forms, hipStream_t st, void *prof_ctx);
+                               const uint8_t *forms, int plan, hipStream_t st, void *prof_ctx);
 bool small_supported(int dtype, int n);
 // circuit-form gates
 hipError_t launch_gate_rx(int dtype, void *psi, int n, int q, double phi, hipStream_t st);

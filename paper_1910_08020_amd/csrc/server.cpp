@@ -349,7 +349,7 @@ void worker_loop(lgt_server *s)
                 for (int j = 0; j < steps && r->step + j < r->n_total; ++j) forms[j] |= r->forms[r->step + j];
             if (enqueue_fused_steps(l.second.first.dtype, sr.lat.n_links, sr.lat.n_plaq,
                                     (const DevInst *)((char *)s->inst_dev + l.first),
-                                    l.second.second, steps, -1, 0, forms.data(), s->stream,
+                                    l.second.second, steps, -1, 0, forms.data(), 0, s->stream,
                                     nullptr) != hipSuccess)
                 dev_fail = true;
         }

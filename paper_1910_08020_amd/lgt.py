@@ -84,6 +84,8 @@ _SIGNATURES = [
     ("lgt_sync", ctypes.c_int, [_VP]),
     ("lgt_set_profiling", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lgt_kernel_stats", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64), _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    ("lgt_tune", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("lgt_plan_describe", ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_size_t]),
     ("lgt_last_error", ctypes.c_char_p, [_VP]),
     ("lgt_batch_evolve", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_VP), ctypes.POINTER(lgt_schedule), ctypes.POINTER(ctypes.c_int), ctypes.c_int64, ctypes.c_int64]),
     ("lgt_server_create", ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)]),
@@ -261,6 +263,16 @@ def lgt_kernel_stats(ctx) -> dict:
     n = ctypes.c_int()
     _check(lib().lgt_kernel_stats(ctx, names, launches, ms, cap, ctypes.byref(n)), ctx)
     return {names[i].decode(): (launches[i], ms[i]) for i in range(n.value)}
+
+
+def lgt_tune(ctx, steps=8):
+    _check(lib().lgt_tune(ctx, steps), ctx)
+
+
+def lgt_plan_describe(ctx) -> str:
+    buf = ctypes.create_string_buffer(512)
+    _check(lib().lgt_plan_describe(ctx, buf, 512), ctx)
+    return buf.value.decode()
 
 
 def lgt_last_error(ctx=None) -> str:

@@ -362,3 +362,34 @@ def test_server_alone_equals_mix():
             e = lgt.lgt_measure(ctx, lgt.LGT_OBS_ENERGY, cx=r.lam, cz=1.0)[0]
         assert abs(e - res.energy) < 1e-6
         assert res.gauss_violation < 1e-4
+
+
+@pytest.mark.parametrize("d,L,dtype", [(2, (3, 3), C64), (2, (2, 5), C128), (3, (2, 2, 2), C64),
+                                       (3, (2, 2, 2), C128)],
+                         ids=["3x3-c64", "2x5-c128", "2x2x2-c64", "2x2x2-c128"])
+def test_tune_keeps_state_and_parity(d, L, dtype):
+    """The autotuner times plans on identity steps: the state is untouched, and the
+    plan it keeps still matches the oracle."""
+    ol = oracle.Lattice(d, L)
+    psi0 = workloads.random_state(ol.N, stream=21)
+    if dtype == C64:
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    n, T = 6, 0.3
+    with gpu_ctx(d, L, dtype, psi0) as ctx:
+        before = get_state(ctx)
+        lgt.lgt_tune(ctx, 4)
+        assert np.array_equal(get_state(ctx), before)
+        assert lgt.lgt_plan_describe(ctx)
+        lgt.lgt_evolve(ctx, lgt.make_schedule(T, n, 0.8, 1.0), SYM, lgt.LGT_FORM_FUSED, 0, n)
+        got = get_state(ctx)
+    want = oracle_evolve(ol, T, n, 0.8, 1.0, SYM, state=psi0)
+    if dtype == C128:
+        assert np.max(np.abs(got - want)) < 1e-10
+    else:
+        assert infidelity(got, want) < 1e-6
+
+
+def test_plan_description_small_state():
+    with gpu_ctx(2, (2, 2), C64) as ctx:
+        assert lgt.lgt_plan_describe(ctx).startswith("small")
+        lgt.lgt_tune(ctx, 2)
