@@ -247,8 +247,8 @@ lgt_status lgt_kernel_stats(lgt_ctx *ctx, const char **names, int64_t *launches,
 
 /*
  * lgt_tune: autotuner for the link-layer pass plan of this context's lattice and dtype.
- * Times each candidate plan (12-bit low tile + register passes; LDS tile passes with the
- * longest or the shortest contiguous rows) over `steps` identity steps on the context's
+ * Times each candidate plan (12-bit or full-size low tiles, high tiles with the longest
+ * or the shortest contiguous rows, register passes) over `steps` identity steps on the context's
  * own state (u = 1, v = 0 and unit phases, which leave every amplitude bit-for-bit
  * unchanged) and keeps the fastest for later evolve calls on this context.  Plans apply
  * the same rotations in a different order, so a tuned context may round differently

@@ -217,30 +217,31 @@ namespace lgt {
 PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
 {
     PassPlan p;
-    if (n_links <= 12) return p;   // handled on chip by the small-state kernel
-    const int low = dtype == LGT_C64 ? 14 : 13;
-    // too few low tiles to fill the GPU: the 12-bit plan gives 4x more workgroups.  The
-    // choice depends on the lattice only, so batched and single runs round identically.
+    if (n_links <= 12) return p;   // handled on chip by the small-state kernels
+    const int big = dtype == LGT_C64 ? 14 : 13;
+    // The default depends on the lattice only, so batched and single runs round
+    // identically: big low tiles when they give at least 64 workgroups, else 12-bit ones.
     (void)n_inst;
-    if (n_links < low) plan = 1;
-    if (plan == 0 && (1 << (n_links - low)) < 64) plan = 1;
-    const bool long_rows = plan != 3;
-    if (plan == 1) {
-        // 12-bit low tile, then register passes of at most 6 (complex64) / 5 bits
-        p.pass[p.n_passes++] = Pass{PASS_LOW12, 0, 12};
+    if (plan == 0) plan = (n_links >= big && (1 << (n_links - big)) >= 64) ? 2 : 1;
+    if (plan == 4) {
+        // the 12-bit LDS tile with 256 threads followed by register passes of <= 6 bits
+        p.pass[p.n_passes++] = Pass{PASS_LOW12, 0, 12, 0};
         const int rest = n_links - 12, hmax = dtype == LGT_C64 ? 6 : 5;
         const int nh = (rest + hmax - 1) / hmax;
         int q = 12;
         for (int i = 0; i < nh; ++i) {
             const int h = rest / nh + (i < rest % nh ? 1 : 0);
-            p.pass[p.n_passes++] = Pass{PASS_HIGH_REG, q, h};
+            p.pass[p.n_passes++] = Pass{PASS_HIGH_REG, q, h, 0};
             q += h;
         }
         return p;
     }
-    // persistent tile passes: one low tile, then as few high tiles as possible, each with
-    // the longest rows its width allows; chunks no tile pass takes go to register passes
+    // persistent tile passes: one low tile (12 bits for plan 1, the largest otherwise), then
+    // as few high tiles as possible with the longest (plans 1, 2) or shortest (3) rows;
+    // chunks no tile pass takes go to register passes
+    const int low = (plan == 1 || n_links < big) ? 12 : big;
     p.pass[p.n_passes++] = Pass{PASS_TILE_LOW, 0, low, 0};
+    const bool long_rows = plan != 3;
     const int rest = n_links - low, reg_max = dtype == LGT_C64 ? 6 : 5;
     const int cb_lo = dtype == LGT_C64 ? 4 : 3;
     const int nh = (rest + 9) / 10;
@@ -254,17 +255,12 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
         }
         if (cb >= 0) p.pass[p.n_passes++] = Pass{PASS_TILE_HIGH, q, h, cb};
         else if (h <= reg_max) p.pass[p.n_passes++] = Pass{PASS_HIGH_REG, q, h, 0};
-        else return plan_passes(n_links, dtype, 1, n_inst);
+        else return plan_passes(n_links, dtype, 4, n_inst);
         q += h;
     }
     return p;
 }
 
-}  // namespace lgt
-
-namespace lgt {
-
-// enqueue `count` fused substeps of n_inst instances whose pointers sit in dev_inst
 std::string describe_plan(const PassPlan &p, int n_links)
 {
     if (p.n_passes == 0) return "small(" + std::to_string(n_links) + " links on chip)";
@@ -317,7 +313,7 @@ hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_
                 break;
             case PASS_TILE_LOW:
                 e = run(KF_TILE_LOW, [&] {
-                    return launch_tile(dtype, dev_inst, n_inst, n, 1, 0, 0, 0, j, pre, post, n_plaq, fm, st);
+                    return launch_tile(dtype, dev_inst, n_inst, n, 1, 0, ps.h, 0, j, pre, post, n_plaq, fm, st);
                 });
                 break;
             case PASS_TILE_HIGH:
@@ -919,7 +915,7 @@ lgt_status lgt_tune(lgt_ctx *c, int steps)
     int best = c->plan;
     float best_ms = 1e30f;
     std::vector<std::string> seen;
-    for (int cand : {1, 2, 3}) {
+    for (int cand : {1, 2, 3, 4}) {
         if (e != hipSuccess) break;
         const std::string d = describe_plan(plan_passes(n, c->dtype, cand, 1), n);
         if (std::find(seen.begin(), seen.end(), d) != seen.end()) continue;

@@ -93,6 +93,32 @@ __device__ __forceinline__ void apply_phase_regs(C *v, uint32_t P0, const uint32
     }
 }
 
+// multiply 16 registers by table[popcount(P0 ^ pr[r])], pr[r] the (uniform) plaquette set
+// of register r's index bits
+template <typename C>
+__device__ __forceinline__ void apply_phase_pr(C *v, uint32_t P0, const uint32_t *pr, const C *table)
+{
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], table[__popc(P0 ^ pr[r])]);
+}
+
+// plaquette sets of the 16 register combinations from the 4 single-bit sets, kept in
+// scalar registers (the sets are the same for every lane)
+__device__ __forceinline__ void reg_sets(const uint32_t *q, uint32_t *pr)
+{
+    uint32_t s[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] = __builtin_amdgcn_readfirstlane(q[k]);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (r & (1 << k)) x ^= s[k];
+        pr[r] = x;
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void load_tables(const DevInst &in, int n_plaq, int pre, int post,
                                             uint32_t *ptab, cplx_t<T> *ph_pre,
@@ -350,45 +376,56 @@ __global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ in
     load(tile, v);   // first tile in flight while the tables are staged
     // tables are only needed by passes that apply a phase
     const bool phased = pre >= 0 || post >= 0;
-    uint32_t qa[4] = {0, 0, 0, 0}, qb[4] = {0, 0, 0, 0};
+    uint32_t pra[16], prb[16];
     if (phased) {
         load_tables<T>(in, n_plaq, pre, post, ptab, ph_pre, ph_post);
         __syncthreads();
+        uint32_t qa[4], qb[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             qa[k] = link_set(gbit(6 + W + k), ptab);
             qb[k] = link_set(gbit(k < W ? 6 + k : 6 + W + k), ptab);
         }
+        reg_sets(qa, pra);
+        reg_sets(qb, prb);
     }
 
-    for (;;) {
-        const uint64_t next = tile + gridDim.x;
-        if (next < n_tiles) load(next, nv);
-        C *tp = psi + tile_base(tile);
-        if (pre >= 0) apply_phase_regs<C, 4>(v, syndrome(tile_base(tile) + thrA, ptab), qa, ph_pre);
-        rot_regs_s<TAN, 15, T, C>(v, tt);
-        rot_lanes<TAN, G::LMASK, T, C>(v, tt);
+    // one tile: rotations, the exchange, the phase, the store
+    auto work = [&](uint64_t t_id, C *x) {
+        C *tp = psi + tile_base(t_id);
+        if (pre >= 0) apply_phase_pr<C>(x, syndrome(tile_base(t_id) + thrA, ptab), pra, ph_pre);
+        rot_regs_s<TAN, 15, T, C>(x, tt);
+        rot_lanes<TAN, G::LMASK, T, C>(x, tt);
         if constexpr (W > 0) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) buf[G::offA(lwA, r)] = v[r];
+            for (int r = 0; r < 16; ++r) buf[G::offA(lwA, r)] = x[r];
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = buf[G::offB(l, w, r)];
+            for (int r = 0; r < 16; ++r) x[r] = buf[G::offB(l, w, r)];
             __syncthreads();
-            rot_regs_s<TAN, (1 << W) - 1, T, C>(v, tt);
+            rot_regs_s<TAN, (1 << W) - 1, T, C>(x, tt);
         }
         if (post >= 0)
-            apply_phase_regs<C, 4>(v, syndrome(tile_base(tile) + (W > 0 ? thrB : thrA), ptab),
-                                   W > 0 ? qb : qa, ph_post);
+            apply_phase_pr<C>(x, syndrome(tile_base(t_id) + (W > 0 ? thrB : thrA), ptab),
+                              W > 0 ? prb : pra, ph_post);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            if constexpr (W > 0) (tp + spread(G::offB(0, 0, r)))[thrB] = v[r];
-            else (tp + spread(r << (6 + W)))[thrA] = v[r];
+            if constexpr (W > 0) (tp + spread(G::offB(0, 0, r)))[thrB] = x[r];
+            else (tp + spread(r << (6 + W)))[thrA] = x[r];
         }
+    };
+    // two register buffers alternate: while one tile is worked on, the next one loads
+    for (;;) {
+        uint64_t next = tile + gridDim.x;
+        if (next < n_tiles) load(next, nv);
+        work(tile, v);
         if (next >= n_tiles) break;
         tile = next;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = nv[r];
+        next = tile + gridDim.x;
+        if (next < n_tiles) load(next, v);
+        work(tile, nv);
+        if (next >= n_tiles) break;
+        tile = next;
     }
 }
 
@@ -917,10 +954,10 @@ static hipError_t launch_pass_t(const DevInst *dev_inst, int n_inst, int n, int 
 
 int pass_wave_bits(int dtype, int low, int h, int cb)
 {
-    // low tile: 10+W bits, W = 4 (complex64) / 3 (complex128).  High tile with rows of
-    // 2^cb amplitudes rotates (6-cb) lane bits + 4 register bits + W wave bits.
+    // low tile of h = 10+W bits, 2 <= W <= 4 (complex64) / 3 (complex128).  High tile with
+    // rows of 2^cb amplitudes rotates (6-cb) lane bits + 4 register bits + W wave bits.
     const int wmax = dtype == LGT_C64 ? 4 : 3;
-    if (low) return wmax;
+    if (low) return (h - 10 >= 2 && h - 10 <= wmax) ? h - 10 : -1;
     const int cb_lo = dtype == LGT_C64 ? 4 : 3;
     if (cb < cb_lo || cb > cb_lo + 1) return -1;
     const int w = h - (10 - cb);
@@ -953,7 +990,11 @@ hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, in
     if (!pass_offsets_fit(dtype, n, low, hb, h, cb)) return hipErrorInvalidValue;
     const int w = pass_wave_bits(dtype, low, h, cb);
     if (dtype == LGT_C64) {
-        if (low) return launch_pass_t<float, 4, 14>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+        if (low) {
+            if (w == 2) return launch_pass_t<float, 2, 12>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+            if (w == 3) return launch_pass_t<float, 3, 13>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+            return launch_pass_t<float, 4, 14>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+        }
         if (cb == 4) {
             LGT_PASS_CASES(float, 4)
             return launch_pass_t<float, 4, 4>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
@@ -961,7 +1002,10 @@ hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, in
         LGT_PASS_CASES(float, 5)
         return launch_pass_t<float, 4, 5>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
     }
-    if (low) return launch_pass_t<double, 3, 13>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+    if (low) {
+        if (w == 2) return launch_pass_t<double, 2, 12>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+        return launch_pass_t<double, 3, 13>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+    }
     if (cb == 3) {
         LGT_PASS_CASES(double, 3)
     } else {

@@ -105,8 +105,9 @@ struct PassPlan {
     int n_passes = 0;
     Pass pass[8];
 };
-// plan = 0: built-in rule (tile passes unless there are too few tiles); 1: 12-bit low
-// tile + register passes; 2: tile passes, longest rows; 3: tile passes, shortest rows
+// plan = 0: built-in rule (2 when the big low tile gives >= 64 workgroups, else 1);
+// 1: 12-bit low tile + high tiles; 2: big low tile + high tiles with the longest rows;
+// 3: big low tile, shortest rows; 4: 12-bit LDS tile + register passes
 PassPlan plan_passes(int n_links, int dtype, int plan = 0, int n_inst = 1);
 std::string describe_plan(const PassPlan &p, int n_links);
 
