@@ -255,9 +255,24 @@ lgt_status lgt_kernel_stats(lgt_ctx *ctx, const char **names, int64_t *launches,
  * from an untuned one (within the precision of the dtype).  States of <= 12 links have
  * a single on-chip kernel and nothing to tune.  1 <= steps <= 1024.
  * lgt_plan_describe: the plan evolve will use, as text (e.g. "tile_low14 | tile_high(...)").
+ *
+ * lgt_set_plan: pick the plan by code, e.g. to reuse what lgt_tune chose in another process
+ * (lgt_get_plan reads it back).  0 = built-in rule; 1 = 12-bit low tile, then high tiles
+ * with the longest rows; 2 = the largest low tile (14 bits complex64, 13 complex128), then
+ * as 1; 3 = as 2 with the shortest rows; 4 = 12-bit LDS tile and register passes only.
+ * Adding LGT_PLAN_NO_MERGE keeps one launch per pass and step.  Without it, tile plans
+ * walk their passes forwards and backwards on alternate steps, so that the pass ending one
+ * step also starts the next and applies both rotations around the phase in one launch
+ * (the X layer is a product of commuting single-link rotations, the product of R_x gates
+ * after eq. (ara), Sec. 2.2): P passes per step become P - 1 plus
+ * one per call.  Every plan gives the same result up to rounding.  E_INVALID for unknown
+ * codes.
  */
+#define LGT_PLAN_NO_MERGE 8
 lgt_status lgt_tune(lgt_ctx *ctx, int steps);
 lgt_status lgt_plan_describe(const lgt_ctx *ctx, char *out, size_t len);
+lgt_status lgt_set_plan(lgt_ctx *ctx, int plan);
+lgt_status lgt_get_plan(const lgt_ctx *ctx, int *plan);
 
 /* Message for the last failure on ctx (ctx may be NULL for create/batch calls). */
 const char *lgt_last_error(const lgt_ctx *ctx);

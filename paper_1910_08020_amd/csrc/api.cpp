@@ -222,6 +222,8 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
     // The default depends on the lattice only, so batched and single runs round
     // identically: big low tiles when they give at least 64 workgroups, else 12-bit ones.
     (void)n_inst;
+    const bool merge = !(plan & kPlanNoMerge);
+    plan &= ~kPlanNoMerge;
     if (plan == 0) plan = (n_links >= big && (1 << (n_links - big)) >= 64) ? 2 : 1;
     if (plan == 4) {
         // the 12-bit LDS tile with 256 threads followed by register passes of <= 6 bits
@@ -258,6 +260,15 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
         else return plan_passes(n_links, dtype, 4, n_inst);
         q += h;
     }
+    // steps merge at the first and the last pass: keep a register pass out of those places
+    const int last = p.n_passes - 1;
+    if (last >= 2 && p.pass[last].kind == PASS_HIGH_REG)
+        for (int i = last - 1; i >= 1; --i)
+            if (p.pass[i].kind == PASS_TILE_HIGH) {
+                std::swap(p.pass[i], p.pass[last]);
+                break;
+            }
+    p.merge = merge && last >= 1 && p.pass[last].kind != PASS_HIGH_REG;
     return p;
 }
 
@@ -278,6 +289,7 @@ std::string describe_plan(const PassPlan &p, int n_links)
         default: s += "reg_high(q" + std::to_string(ps.q0) + ",h" + std::to_string(ps.h) + ")";
         }
     }
+    if (p.merge) s += " ; steps merged";
     return s;
 }
 
@@ -297,38 +309,49 @@ hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_
         });
     }
     const PassPlan plan = plan_passes(n, dtype, plan_sel, n_inst);
+    const int np = plan.n_passes;
+    // merged plans walk the passes forwards and backwards in turn, so a step's last pass
+    // is the next step's first: one launch applies both rotations around the phase
+    bool fwd = true, merged_in = false;
     for (int j = 0; j < count; ++j) {
-        const int fm = forms ? (forms[j] ? forms[j] : 1) : 3;
-        for (int p = 0; p < plan.n_passes; ++p) {
-            const Pass &ps = plan.pass[p];
-            const bool last = (p == plan.n_passes - 1);
+        auto form_at = [&](int i) { return forms ? ((forms[i] & 3) ? (forms[i] & 3) : 1) : 3; };
+        const bool merge_out = plan.merge && j + 1 < count;
+        const int fm = form_at(j) | (merge_out ? form_at(j + 1) << 2 : 0);
+        for (int k = merged_in ? 1 : 0; k < np; ++k) {
+            const Pass &ps = plan.pass[fwd ? k : np - 1 - k];
+            const bool last = (k == np - 1);
             const int post = last ? j + post_off : -1;
-            const int pre = (p == 0 && j == 0) ? pre_first : -1;
+            const int pre = (k == 0 && j == 0) ? pre_first : -1;
+            const int mg = (last && merge_out) ? 1 : 0;
             hipError_t e;
             switch (ps.kind) {
             case PASS_LOW12:
+                if (mg) return hipErrorInvalidValue;   // only tile passes merge steps
                 e = run(KF_LOW, [&] {
                     return launch_low(dtype, dev_inst, n_inst, n, 12, j, pre, post, n_plaq, st);
                 });
                 break;
             case PASS_TILE_LOW:
                 e = run(KF_TILE_LOW, [&] {
-                    return launch_tile(dtype, dev_inst, n_inst, n, 1, 0, ps.h, 0, j, pre, post, n_plaq, fm, st);
+                    return launch_tile(dtype, dev_inst, n_inst, n, 1, 0, ps.h, 0, j, pre, post, n_plaq, fm, mg, st);
                 });
                 break;
             case PASS_TILE_HIGH:
                 e = run(KF_TILE_HIGH, [&] {
-                    return launch_tile(dtype, dev_inst, n_inst, n, 0, ps.q0, ps.h, ps.cb, j, pre, post, n_plaq, fm, st);
+                    return launch_tile(dtype, dev_inst, n_inst, n, 0, ps.q0, ps.h, ps.cb, j, pre, post, n_plaq, fm, mg, st);
                 });
                 break;
             default:
-                if (pre >= 0) return hipErrorInvalidValue;   // register passes never come first
+                // register passes never come first and never merge steps
+                if (pre >= 0 || mg) return hipErrorInvalidValue;
                 e = run(KF_HIGH, [&] {
                     return launch_high(dtype, dev_inst, n_inst, n, ps.q0, ps.h, j, post, n_plaq, st);
                 });
             }
             if (e != hipSuccess) return e;
         }
+        merged_in = merge_out;
+        if (plan.merge) fwd = !fwd;
     }
     return hipSuccess;
 }
@@ -342,11 +365,11 @@ static hipError_t enqueue_fused(lgt_ctx *c, const DevInst *dev_inst, int n_inst,
                                pre_phase ? 0 : -1, pre_phase, forms, c->plan, c->stream, c);
 }
 
-// bit 0: tan form (u == 1) of the factored link rotation, bit 1: cot form
+// kFormTan: tan form (u == 1) of the factored link rotation, kFormCot: cot form
 static void or_forms(const StepTables &st, std::vector<uint8_t> &forms)
 {
     if (forms.size() < (size_t)st.n_steps) forms.resize(st.n_steps, 0);
-    for (int j = 0; j < st.n_steps; ++j) forms[j] |= (st.rot_u[j] == 1.0) ? 1 : 2;
+    for (int j = 0; j < st.n_steps; ++j) forms[j] |= (st.rot_u[j] == 1.0) ? kFormTan : kFormCot;
 }
 
 static lgt_status create_common(int d, const int *L, int periodic, lgt_dtype dtype, void *buf,
@@ -864,6 +887,22 @@ lgt_status lgt_plan_describe(const lgt_ctx *c, char *out, size_t len)
     const std::string d = describe_plan(plan_passes(c->lat.n_links, c->dtype, c->plan, 1), c->lat.n_links);
     std::snprintf(out, len, "%s", d.c_str());
     return d.size() < len ? LGT_OK : fail(const_cast<lgt_ctx *>(c), LGT_E_INVALID, "buffer too short");
+}
+
+lgt_status lgt_set_plan(lgt_ctx *c, int plan)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (plan < 0 || (plan & ~kPlanNoMerge) > 4) return fail(c, LGT_E_INVALID, "unknown plan code");
+    c->plan = plan;
+    return LGT_OK;
+}
+
+lgt_status lgt_get_plan(const lgt_ctx *c, int *plan)
+{
+    if (!c || !plan) return fail(nullptr, LGT_E_INVALID, "null argument");
+    *plan = c->plan;
+    return LGT_OK;
 }
 
 lgt_status lgt_tune(lgt_ctx *c, int steps)

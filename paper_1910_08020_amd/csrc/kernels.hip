@@ -28,6 +28,42 @@ template <> struct CV<double> { using type = double2; };
 template <typename T>
 using cplx_t = typename CV<T>::type;
 
+// Pointers taken from DevInst records are generic; casting them to the global address
+// space makes the compiler emit global (not flat) loads and stores, which count only
+// against vmcnt, so waits on LDS traffic do not also wait for prefetched tiles.
+template <typename X>
+using gp = __attribute__((address_space(1))) X *;
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
+
+// element loads and stores through global pointers (pairs as native 2-vectors)
+template <typename T>
+__device__ __forceinline__ cplx_t<T> ldg(gp<const cplx_t<T>> p)
+{
+    const vec2<T> v = *(gp<const vec2<T>>)p;
+    cplx_t<T> c;
+    c.x = v.x;
+    c.y = v.y;
+    return c;
+}
+__device__ __forceinline__ float2 ldg(gp<const float2> p) { return ldg<float>(p); }
+__device__ __forceinline__ double2 ldg(gp<const double2> p) { return ldg<double>(p); }
+template <typename T>
+__device__ __forceinline__ RotParam<T> ldg(gp<const RotParam<T>> p)
+{
+    const vec2<T> v = *(gp<const vec2<T>>)p;
+    return RotParam<T>{v.x, v.y};
+}
+template <typename C>
+__device__ __forceinline__ void stg(gp<C> p, const C &c)
+{
+    using T = std::remove_reference_t<decltype(c.x)>;
+    vec2<T> v;
+    v.x = c.x;
+    v.y = c.y;
+    *(gp<vec2<T>>)p = v;
+}
+
 constexpr int kPtabWords = kParityBytes * 256;
 
 __device__ __forceinline__ uint32_t syndrome(uint64_t b, const uint32_t *tab)
@@ -125,15 +161,16 @@ __device__ __forceinline__ void load_tables(const DevInst &in, int n_plaq, int p
                                             cplx_t<T> *ph_post)
 {
     using C = cplx_t<T>;
-    for (int i = threadIdx.x; i < kPtabWords; i += blockDim.x) ptab[i] = in.ptab[i];
-    const C *ph = (const C *)in.phase;
+    const gp<const uint32_t> gtab = (gp<const uint32_t>)in.ptab;
+    for (int i = threadIdx.x; i < kPtabWords; i += blockDim.x) ptab[i] = gtab[i];
+    const gp<const C> ph = (gp<const C>)in.phase;
     const int np1 = n_plaq + 1;
     if (pre >= 0)
         for (int i = threadIdx.x; i < np1; i += blockDim.x)
-            ph_pre[i] = ph[(size_t)(in.ph0 + pre) * np1 + i];
+            ph_pre[i] = ldg(ph + (size_t)(in.ph0 + pre) * np1 + i);
     if (post >= 0)
         for (int i = threadIdx.x; i < np1; i += blockDim.x)
-            ph_post[i] = ph[(size_t)(in.ph0 + post) * np1 + i];
+            ph_post[i] = ldg(ph + (size_t)(in.ph0 + post) * np1 + i);
 }
 
 // ---------------------------------------------------------------------------
@@ -157,17 +194,17 @@ __global__ __launch_bounds__(kLowThreads) void k_low(const DevInst *__restrict__
 
     const DevInst in = insts[blockIdx.y];
     if (in.step0 + step >= in.n_total) return;   // instance already finished (uniform per block)
-    C *__restrict__ psi = (C *)in.psi;
+    const gp<C> psi = (gp<C>)in.psi;
     const int t = threadIdx.x;
     const uint64_t base = (uint64_t)blockIdx.x << kLowBits;
-    const RotParam<T> rp = ((const RotParam<T> *)in.rot)[in.step0 + step];
+    const RotParam<T> rp = ldg((gp<const RotParam<T>>)in.rot + (in.step0 + step));
     load_tables<T>(in, n_plaq, pre, post, ptab, ph_pre, ph_post);
     __syncthreads();
 
     C v[16];
     // round 1: registers hold tile bits 8..11, coalesced loads
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = psi[base + t + (r << 8)];
+    for (int r = 0; r < 16; ++r) v[r] = ldg(psi + (base + t + (r << 8)));
     if (pre >= 0) {
         uint32_t qs[4];
 #pragma unroll
@@ -197,7 +234,7 @@ __global__ __launch_bounds__(kLowThreads) void k_low(const DevInst *__restrict__
         apply_phase_regs<C, 4>(v, syndrome(base + ((uint64_t)t << 4), ptab), qs, ph_post);
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r) psi[base + ((uint64_t)t << 4) + r] = v[r];
+    for (int r = 0; r < 16; ++r) stg(psi + (base + ((uint64_t)t << 4) + r), v[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -329,7 +366,11 @@ struct PassGeom {
     }
 };
 
-template <typename T, int W, int ROWB, bool TAN>
+// TAN / TN: rotation form of step and step + 1.  MERGE: the launch also applies the next
+// step's rotation of the same tile bits after the phase (consecutive steps whose passes run
+// in opposite directions share this pass).  An instance whose last step is `step` stops
+// after the phase; it runs in the launch with TN == TAN.
+template <typename T, int W, int ROWB, bool TAN, bool TN, bool MERGE>
 __global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ insts, int n, int hb,
                                                   int step, int pre, int post, int n_plaq)
 {
@@ -343,10 +384,25 @@ __global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ in
 
     const DevInst in = insts[blockIdx.y];
     if (in.step0 + step >= in.n_total) return;   // instance already finished (uniform per block)
-    const RotParam<T> rp = ((const RotParam<T> *)in.rot)[in.step0 + step];
+    const gp<const RotParam<T>> rot = (gp<const RotParam<T>>)in.rot;
+    const RotParam<T> rp = ldg(rot + (in.step0 + step));
     if ((rp.u == T(1)) != TAN) return;           // the other rotation form has its own launch
-    C *__restrict__ psi = (C *)in.psi;
+    const gp<C> psi = (gp<C>)in.psi;
     const T tt = TAN ? rp.v : rp.u;
+    T tn = tt;
+    bool more = false;                           // merged and the instance has step + 1
+    if constexpr (MERGE) {
+        more = in.step0 + step + 1 < in.n_total;
+        if (more) {
+            const RotParam<T> rq = ldg(rot + (in.step0 + step + 1));
+            if ((rq.u == T(1)) != TN) return;
+            tn = TN ? rq.v : rq.u;
+        } else if (TN != TAN) {
+            return;
+        }
+    } else {
+        static_assert(MERGE || TN == TAN, "single-step passes have one form");
+    }
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t n_tiles = 1ull << (n - TB);
     const int lowb = LOW ? 0 : hb - CB;
@@ -366,19 +422,30 @@ __global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ in
     // per-thread element offsets fit 32 bits (checked by the launcher)
     const uint32_t thrA = (uint32_t)spread(lwA), thrB = (uint32_t)spread(lwB);
     auto load = [&](uint64_t tile, C *dst) {
-        const C *tp = psi + tile_base(tile);
+        const gp<const C> tp = psi + tile_base(tile);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) dst[r] = (tp + spread(r << (6 + W)))[thrA];
+        for (int r = 0; r < 16; ++r) dst[r] = ldg(tp + spread(r << (6 + W)) + thrA);
+    };
+    // Prefetch of the tile after `tile` when there is one; otherwise 16 loads of the
+    // tile's first row (cached, values unused), so that every tile is worked on with the
+    // same number of memory operations in flight and the wait before it only covers its
+    // own loads, not the previous tile's stores.
+    auto prefetch = [&](uint64_t tile, uint64_t next, C *dst) {
+        const bool real = next < n_tiles;
+        const gp<const C> tp = psi + tile_base(real ? next : tile);
+        const uint32_t lo = real ? thrA : (uint32_t)l;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[r] = ldg(tp + (real ? spread(r << (6 + W)) : 0) + lo);
     };
     uint64_t tile = blockIdx.x;
     if (tile >= n_tiles) return;
     C v[16], nv[16];
     load(tile, v);   // first tile in flight while the tables are staged
     // tables are only needed by passes that apply a phase
-    const bool phased = pre >= 0 || post >= 0;
+    const bool phased = MERGE || pre >= 0 || post >= 0;
     uint32_t pra[16], prb[16];
     if (phased) {
-        load_tables<T>(in, n_plaq, pre, post, ptab, ph_pre, ph_post);
+        load_tables<T>(in, n_plaq, MERGE ? -1 : pre, post, ptab, ph_pre, ph_post);
         __syncthreads();
         uint32_t qa[4], qb[4];
 #pragma unroll
@@ -390,10 +457,12 @@ __global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ in
         reg_sets(qb, prb);
     }
 
-    // one tile: rotations, the exchange, the phase, the store
-    auto work = [&](uint64_t t_id, C *x) {
-        C *tp = psi + tile_base(t_id);
-        if (pre >= 0) apply_phase_pr<C>(x, syndrome(tile_base(t_id) + thrA, ptab), pra, ph_pre);
+    // one tile: rotations, the exchange, the phase, the store (merged: the next step's
+    // rotations after the phase, and a second exchange back to the load layout)
+    auto work = [&](uint64_t t_id, C *x) __attribute__((always_inline)) {
+        const gp<C> tp = psi + tile_base(t_id);
+        if (!MERGE && pre >= 0)
+            apply_phase_pr<C>(x, syndrome(tile_base(t_id) + thrA, ptab), pra, ph_pre);
         rot_regs_s<TAN, 15, T, C>(x, tt);
         rot_lanes<TAN, G::LMASK, T, C>(x, tt);
         if constexpr (W > 0) {
@@ -405,27 +474,48 @@ __global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ in
             __syncthreads();
             rot_regs_s<TAN, (1 << W) - 1, T, C>(x, tt);
         }
-        if (post >= 0)
+        if (MERGE || post >= 0)
             apply_phase_pr<C>(x, syndrome(tile_base(t_id) + (W > 0 ? thrB : thrA), ptab),
                               W > 0 ? prb : pra, ph_post);
+        if (MERGE && more) {
+            // layout B holds every tile bit but its wave bits in registers or lanes
+            rot_regs_s<TN, 15, T, C>(x, tn);
+            rot_lanes<TN, G::LMASK, T, C>(x, tn);
+            if constexpr (W > 0) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if constexpr (W > 0) (tp + spread(G::offB(0, 0, r)))[thrB] = x[r];
-            else (tp + spread(r << (6 + W)))[thrA] = x[r];
+                for (int r = 0; r < 16; ++r) buf[G::offB(l, w, r)] = x[r];
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < 16; ++r) x[r] = buf[G::offA(lwA, r)];
+                __syncthreads();
+                rot_regs_s<TN, (1 << W) - 1, T, C>(x, tn);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) stg(tp + spread(r << (6 + W)) + thrA, x[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                if constexpr (W > 0) stg(tp + spread(G::offB(0, 0, r)) + thrB, x[r]);
+                else stg(tp + spread(r << (6 + W)) + thrA, x[r]);
+            }
         }
     };
-    // two register buffers alternate: while one tile is worked on, the next one loads
-    for (;;) {
-        uint64_t next = tile + gridDim.x;
-        if (next < n_tiles) load(next, nv);
-        work(tile, v);
-        if (next >= n_tiles) break;
+    // two register buffers alternate: while one tile is worked on, the next one loads.
+    // The first tile is peeled so that every work in the loop follows the same sequence
+    // (own loads, previous stores, next loads) on every path.
+    uint64_t next = tile + gridDim.x;
+    prefetch(tile, next, nv);
+    work(tile, v);
+    while (next < n_tiles) {
         tile = next;
         next = tile + gridDim.x;
-        if (next < n_tiles) load(next, v);
+        prefetch(tile, next, v);
         work(tile, nv);
         if (next >= n_tiles) break;
         tile = next;
+        next = tile + gridDim.x;
+        prefetch(tile, next, nv);
+        work(tile, v);
     }
 }
 
@@ -443,8 +533,8 @@ __global__ __launch_bounds__(kHighThreads) void k_high(const DevInst *__restrict
     __shared__ C ph_post[kMaxPlaq + 1];
     const DevInst in = insts[blockIdx.y];
     if (in.step0 + step >= in.n_total) return;   // instance already finished (uniform per block)
-    C *__restrict__ psi = (C *)in.psi;
-    const RotParam<T> rp = ((const RotParam<T> *)in.rot)[in.step0 + step];
+    const gp<C> psi = (gp<C>)in.psi;
+    const RotParam<T> rp = ldg((gp<const RotParam<T>>)in.rot + (in.step0 + step));
     if (post >= 0) {
         load_tables<T>(in, n_plaq, -1, post, ptab, nullptr, ph_post);
         __syncthreads();
@@ -454,7 +544,7 @@ __global__ __launch_bounds__(kHighThreads) void k_high(const DevInst *__restrict
     const uint64_t base = (g & lowmask) | ((g >> q0) << (q0 + H));
     C v[1 << H];
 #pragma unroll
-    for (int r = 0; r < (1 << H); ++r) v[r] = psi[base + ((uint64_t)r << q0)];
+    for (int r = 0; r < (1 << H); ++r) v[r] = ldg(psi + (base + ((uint64_t)r << q0)));
     rot_regs<T, C, H>(v, rp.u, rp.v);
     if (post >= 0) {
         uint32_t qs[H];
@@ -463,7 +553,7 @@ __global__ __launch_bounds__(kHighThreads) void k_high(const DevInst *__restrict
         apply_phase_regs<C, H>(v, syndrome(base, ptab), qs, ph_post);
     }
 #pragma unroll
-    for (int r = 0; r < (1 << H); ++r) psi[base + ((uint64_t)r << q0)] = v[r];
+    for (int r = 0; r < (1 << H); ++r) stg(psi + (base + ((uint64_t)r << q0)), v[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -479,7 +569,7 @@ __global__ __launch_bounds__(256) void k_phase(const DevInst *__restrict__ insts
     const DevInst in = insts[blockIdx.y];
     load_tables<T>(in, n_plaq, -1, idx, ptab, nullptr, ph);
     __syncthreads();
-    C *__restrict__ psi = (C *)in.psi;
+    const gp<C> psi = (gp<C>)in.psi;
     const uint64_t dim = 1ull << n;
     const int nb = n < 4 ? n : 4;
     uint32_t qs[4];
@@ -495,7 +585,7 @@ __global__ __launch_bounds__(256) void k_phase(const DevInst *__restrict__ insts
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (r & (1 << k)) P ^= qs[k];
-                psi[base + r] = cmul(psi[base + r], ph[__popc(P)]);
+                stg(psi + (base + r), cmul(ldg(psi + (base + r)), ph[__popc(P)]));
             }
         }
     }
@@ -517,28 +607,28 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(const DevInst *__restri
     __shared__ uint8_t syn[1 << 12];
     __shared__ C ph[kMaxPlaq + 1];
     const DevInst in = insts[blockIdx.x];
-    C *__restrict__ psi = (C *)in.psi;
+    const gp<C> psi = (gp<C>)in.psi;
     const int dim = 1 << n, t = threadIdx.x;
     const int np1 = n_plaq + 1;
-    const C *phase = (const C *)in.phase;
-    const RotParam<T> *rot = (const RotParam<T> *)in.rot;
-    for (int i = t; i < kPtabWords; i += kSmallThreads) ptab[i] = in.ptab[i];
+    const gp<const C> phase = (gp<const C>)in.phase;
+    const gp<const RotParam<T>> rot = (gp<const RotParam<T>>)in.rot;
+    for (int i = t; i < kPtabWords; i += kSmallThreads) ptab[i] = ((gp<const uint32_t>)in.ptab)[i];
     __syncthreads();
     for (int b = t; b < dim; b += kSmallThreads) {
-        a[b] = psi[b];
+        a[b] = ldg(psi + b);
         syn[b] = (uint8_t)__popc(syndrome((uint64_t)b, ptab));
     }
     int k = in.ph0;
     const int steps = min(n_steps, in.n_total - in.step0);
     if (pre) {
-        for (int i = t; i < np1; i += kSmallThreads) ph[i] = phase[(size_t)k * np1 + i];
+        for (int i = t; i < np1; i += kSmallThreads) ph[i] = ldg(phase + ((size_t)k * np1 + i));
         __syncthreads();
         for (int b = t; b < dim; b += kSmallThreads) a[b] = cmul(a[b], ph[syn[b]]);
         ++k;
     }
     __syncthreads();
     for (int j = 0; j < steps; ++j, ++k) {
-        const RotParam<T> rp = rot[in.step0 + j];
+        const RotParam<T> rp = ldg(rot + (in.step0 + j));
         for (int q = 0; q < n; ++q) {
             const int lo = (1 << q) - 1;
             for (int p = t; p < (dim >> 1); p += kSmallThreads) {
@@ -547,12 +637,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(const DevInst *__restri
             }
             __syncthreads();
         }
-        for (int i = t; i < np1; i += kSmallThreads) ph[i] = phase[(size_t)k * np1 + i];
+        for (int i = t; i < np1; i += kSmallThreads) ph[i] = ldg(phase + ((size_t)k * np1 + i));
         __syncthreads();
         for (int b = t; b < dim; b += kSmallThreads) a[b] = cmul(a[b], ph[syn[b]]);
         __syncthreads();
     }
-    for (int b = t; b < dim; b += kSmallThreads) psi[b] = a[b];
+    for (int b = t; b < dim; b += kSmallThreads) stg(psi + b, a[b]);
 }
 
 // ---------------------------------------------------------------------------
@@ -601,21 +691,21 @@ __global__ __launch_bounds__(64) void k_wave(const DevInst *__restrict__ insts, 
     __shared__ uint32_t ptab[kPtabWords];
     __shared__ C ph[kMaxPlaq + 1];
     const DevInst in = insts[blockIdx.x];
-    C *__restrict__ psi = (C *)in.psi;
+    const gp<C> psi = (gp<C>)in.psi;
     const int l = threadIdx.x, np1 = n_plaq + 1;
-    const C *phase = (const C *)in.phase;
-    const RotParam<T> *rot = (const RotParam<T> *)in.rot;
-    for (int i = l; i < kPtabWords; i += 64) ptab[i] = in.ptab[i];
+    const gp<const C> phase = (gp<const C>)in.phase;
+    const gp<const RotParam<T>> rot = (gp<const RotParam<T>>)in.rot;
+    for (int i = l; i < kPtabWords; i += 64) ptab[i] = ((gp<const uint32_t>)in.ptab)[i];
     __syncthreads();
     C v[R];
     int m[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        v[r] = psi[l | (r << 6)];
+        v[r] = ldg(psi + (l | (r << 6)));
         m[r] = __popc(syndrome((uint64_t)(l | (r << 6)), ptab));
     }
     auto phase_step = [&](int k) {
-        if (l < np1) ph[l] = phase[(size_t)k * np1 + l];
+        if (l < np1) ph[l] = ldg(phase + ((size_t)k * np1 + l));
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = cmul(v[r], ph[m[r]]);
@@ -625,13 +715,13 @@ __global__ __launch_bounds__(64) void k_wave(const DevInst *__restrict__ insts, 
     const int steps = min(n_steps, in.n_total - in.step0);
     if (pre) phase_step(k++);
     for (int j = 0; j < steps; ++j, ++k) {
-        const RotParam<T> rp = rot[in.step0 + j];
+        const RotParam<T> rp = ldg(rot + (in.step0 + j));
         if (rp.u == T(1)) wave_layer<true, RB, T, C>(v, rp.v);
         else wave_layer<false, RB, T, C>(v, rp.u);
         phase_step(k);
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) psi[l | (r << 6)] = v[r];
+    for (int r = 0; r < R; ++r) stg(psi + (l | (r << 6)), v[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -933,7 +1023,7 @@ hipError_t launch_low(int dtype, const DevInst *dev_inst, int n_inst, int n, int
 
 template <typename T, int W, int ROWB>
 static hipError_t launch_pass_t(const DevInst *dev_inst, int n_inst, int n, int hb, int step,
-                                int pre, int post, int n_plaq, int forms, hipStream_t st)
+                                int pre, int post, int n_plaq, int forms, int merge, hipStream_t st)
 {
     constexpr int TB = 10 + W;
     const uint64_t n_tiles = 1ull << (n - TB);
@@ -945,10 +1035,27 @@ static hipError_t launch_pass_t(const DevInst *dev_inst, int n_inst, int n, int 
     if (slots < 1) slots = 1;
     const uint64_t grid = n_tiles < slots ? n_tiles : slots;
     const dim3 g((unsigned)grid, (unsigned)n_inst), b(64 << W);
+    if (merge) {
+        // forms: bits 0-1 the forms of `step`, bits 2-3 those of step + 1; every form pair
+        // that some instance may have gets a launch, and each instance runs in exactly one
+        if (pre >= 0 || post < 0) return hipErrorInvalidValue;   // merged: one phase between
+        const int fa = forms & 3, fb = (forms >> 2) & 3;
+        if (fa & 1) {
+            hipLaunchKernelGGL((k_pass<T, W, ROWB, true, true, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+            if (fb & 2)
+                hipLaunchKernelGGL((k_pass<T, W, ROWB, true, false, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+        }
+        if (fa & 2) {
+            hipLaunchKernelGGL((k_pass<T, W, ROWB, false, false, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+            if (fb & 1)
+                hipLaunchKernelGGL((k_pass<T, W, ROWB, false, true, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+        }
+        return hipGetLastError();
+    }
     if (forms & 1)
-        hipLaunchKernelGGL((k_pass<T, W, ROWB, true>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
+        hipLaunchKernelGGL((k_pass<T, W, ROWB, true, true, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
     if (forms & 2)
-        hipLaunchKernelGGL((k_pass<T, W, ROWB, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
+        hipLaunchKernelGGL((k_pass<T, W, ROWB, false, false, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
     return hipGetLastError();
 }
 
@@ -976,35 +1083,35 @@ bool pass_offsets_fit(int dtype, int n, int low, int hb, int h, int cb)
 
 #define LGT_PASS_CASES(T, CB)                                                                   \
     switch (w) {                                                                                \
-    case 0: return launch_pass_t<T, 0, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st); \
-    case 1: return launch_pass_t<T, 1, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st); \
-    case 2: return launch_pass_t<T, 2, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st); \
-    case 3: return launch_pass_t<T, 3, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st); \
+    case 0: return launch_pass_t<T, 0, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st); \
+    case 1: return launch_pass_t<T, 1, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st); \
+    case 2: return launch_pass_t<T, 2, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st); \
+    case 3: return launch_pass_t<T, 3, CB>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st); \
     default: break;                                                                             \
     }
 
 hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, int low, int hb,
                        int h, int cb, int step, int pre, int post, int n_plaq, int forms,
-                       hipStream_t st)
+                       int merge, hipStream_t st)
 {
     if (!pass_offsets_fit(dtype, n, low, hb, h, cb)) return hipErrorInvalidValue;
     const int w = pass_wave_bits(dtype, low, h, cb);
     if (dtype == LGT_C64) {
         if (low) {
-            if (w == 2) return launch_pass_t<float, 2, 12>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
-            if (w == 3) return launch_pass_t<float, 3, 13>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
-            return launch_pass_t<float, 4, 14>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+            if (w == 2) return launch_pass_t<float, 2, 12>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, merge, st);
+            if (w == 3) return launch_pass_t<float, 3, 13>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, merge, st);
+            return launch_pass_t<float, 4, 14>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, merge, st);
         }
         if (cb == 4) {
             LGT_PASS_CASES(float, 4)
-            return launch_pass_t<float, 4, 4>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+            return launch_pass_t<float, 4, 4>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st);
         }
         LGT_PASS_CASES(float, 5)
-        return launch_pass_t<float, 4, 5>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, st);
+        return launch_pass_t<float, 4, 5>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st);
     }
     if (low) {
-        if (w == 2) return launch_pass_t<double, 2, 12>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
-        return launch_pass_t<double, 3, 13>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, st);
+        if (w == 2) return launch_pass_t<double, 2, 12>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, merge, st);
+        return launch_pass_t<double, 3, 13>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, merge, st);
     }
     if (cb == 3) {
         LGT_PASS_CASES(double, 3)

@@ -104,7 +104,12 @@ struct Pass {
 struct PassPlan {
     int n_passes = 0;
     Pass pass[8];
+    // consecutive steps run their passes in alternating order, and the pass that ends one
+    // step and starts the next applies both rotations around the phase in one launch
+    bool merge = false;
 };
+// plan code flag: keep one launch per pass and step (no merged steps)
+constexpr int kPlanNoMerge = 8;
 // plan = 0: built-in rule (2 when the big low tile gives >= 64 workgroups, else 1);
 // 1: 12-bit low tile + high tiles; 2: big low tile + high tiles with the longest rows;
 // 3: big low tile, shortest rows; 4: 12-bit LDS tile + register passes
@@ -131,9 +136,11 @@ hipError_t launch_high(int dtype, const DevInst *dev_inst, int n_inst, int n, in
 // persistent tile pass; forms: bit 0 = launch for tan-form steps, bit 1 = cot-form steps.
 // High passes keep rows of 2^cb amplitudes contiguous (cb = 4 or 5 for complex64,
 // 3 or 4 for complex128) and rotate index bits [hb, hb+h).
+// merge = 1: rotation of `step`, the phase `post`, then the rotation of step + 1 (pre = -1);
+// forms then holds the forms of step + 1 in bits 2-3.
 hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, int low, int hb,
                        int h, int cb, int step, int pre, int post, int n_plaq, int forms,
-                       hipStream_t st);
+                       int merge, hipStream_t st);
 // wave bits of the tile pass rotating h bits with rows of 2^cb, -1 if no such pass
 int pass_wave_bits(int dtype, int low, int h, int cb);
 bool pass_offsets_fit(int dtype, int n, int low, int hb, int h, int cb);
@@ -145,7 +152,8 @@ hipError_t launch_small(int dtype, const DevInst *dev_inst, int n_inst, int n, i
                         int pre_phase, int n_plaq, hipStream_t st);
 // enqueue `count` fused substeps for n_inst instances (api.cpp); pre_first: phase index
 // applied before the first link layer or -1; the phase after layer j is post_off + j
-// forms[j]: bit 0 if some instance's link layer j uses the tan form, bit 1 the cot form
+// forms[j]: kFormTan if some instance's link layer j uses the tan form, kFormCot the cot form
+constexpr uint8_t kFormTan = 1, kFormCot = 2;
 hipError_t enqueue_fused_steps(int dtype, int n_links, int n_plaq, const DevInst *dev_inst,
                                int n_inst, int count, int pre_first, int post_off,
                                const uint8_t *forms, int plan, hipStream_t st, void *prof_ctx);

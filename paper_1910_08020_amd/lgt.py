@@ -20,6 +20,7 @@ LGT_ORDER_TROTTER, LGT_ORDER_SYMMETRIC = 1, 2
 LGT_FORM_FUSED, LGT_FORM_CIRCUIT = 0, 1
 LGT_INIT_PLUS, LGT_INIT_ZGROUND, LGT_INIT_BASIS = 0, 1, 2
 LGT_RAMP_PLAQ, LGT_RAMP_COUPLING, LGT_RAMP_EXPLICIT = 0, 1, 2
+LGT_PLAN_NO_MERGE = 8
 (LGT_OBS_NORM, LGT_OBS_Z, LGT_OBS_X, LGT_OBS_PLAQ, LGT_OBS_STAR, LGT_OBS_SIGMAX, LGT_OBS_SIGMAZ,
  LGT_OBS_ENERGY, LGT_OBS_ZDOS) = range(9)
 
@@ -86,6 +87,8 @@ _SIGNATURES = [
     ("lgt_kernel_stats", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64), _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     ("lgt_tune", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lgt_plan_describe", ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_size_t]),
+    ("lgt_set_plan", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("lgt_get_plan", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int)]),
     ("lgt_last_error", ctypes.c_char_p, [_VP]),
     ("lgt_batch_evolve", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_VP), ctypes.POINTER(lgt_schedule), ctypes.POINTER(ctypes.c_int), ctypes.c_int64, ctypes.c_int64]),
     ("lgt_server_create", ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)]),
@@ -273,6 +276,16 @@ def lgt_plan_describe(ctx) -> str:
     buf = ctypes.create_string_buffer(512)
     _check(lib().lgt_plan_describe(ctx, buf, 512), ctx)
     return buf.value.decode()
+
+
+def lgt_set_plan(ctx, plan: int):
+    _check(lib().lgt_set_plan(ctx, plan), ctx)
+
+
+def lgt_get_plan(ctx) -> int:
+    p = ctypes.c_int()
+    _check(lib().lgt_get_plan(ctx, ctypes.byref(p)), ctx)
+    return p.value
 
 
 def lgt_last_error(ctx=None) -> str:

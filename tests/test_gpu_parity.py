@@ -393,3 +393,72 @@ def test_plan_description_small_state():
     with gpu_ctx(2, (2, 2), C64) as ctx:
         assert lgt.lgt_plan_describe(ctx).startswith("small")
         lgt.lgt_tune(ctx, 2)
+
+
+PLANS = [0, 1, 2, 3, 4, lgt.LGT_PLAN_NO_MERGE, 2 | lgt.LGT_PLAN_NO_MERGE]
+
+
+@pytest.mark.parametrize("order", [TROT, SYM], ids=["trotter", "symmetric"])
+@pytest.mark.parametrize("d,L", [(2, (2, 4)), (2, (3, 4)), (3, (2, 2, 2))],
+                         ids=["2x4", "3x4", "2x2x2"])
+def test_every_plan_matches_oracle(d, L, order):
+    """Merged steps (passes alternating direction), unmerged plans and the register-pass
+    plan all apply the same product of rotations and phases."""
+    ol = oracle.Lattice(d, L)
+    psi0 = workloads.random_state(ol.N, stream=31)
+    n, T = 7, 0.35
+    want = oracle_evolve(ol, T, n, 0.9, 1.0, order, state=psi0)
+    for plan in PLANS:
+        with gpu_ctx(d, L, C128, psi0) as ctx:
+            lgt.lgt_set_plan(ctx, plan)
+            assert lgt.lgt_get_plan(ctx) == plan
+            desc = lgt.lgt_plan_describe(ctx)
+            if plan & lgt.LGT_PLAN_NO_MERGE or plan == 4:
+                assert "steps merged" not in desc, desc
+            elif ol.n_links == 24:
+                assert "steps merged" in desc, desc
+            lgt.lgt_evolve(ctx, lgt.make_schedule(T, n, 0.9, 1.0), order, lgt.LGT_FORM_FUSED, 0, n)
+            got = get_state(ctx)
+        assert np.max(np.abs(got - want)) < 1e-10, (plan, desc)
+
+
+def test_set_plan_rejects_unknown_codes():
+    with gpu_ctx(2, (2, 4), C64) as ctx:
+        for bad in (-1, 5, 7, 13, 16):
+            with pytest.raises(lgt.LgtError) as ex:
+                lgt.lgt_set_plan(ctx, bad)
+            assert ex.value.status == lgt.LGT_E_INVALID
+
+
+@pytest.mark.parametrize("d,L", [(2, (2, 4)), (3, (2, 2, 2))], ids=["2x4", "2x2x2"])
+def test_rotation_form_changes_inside_a_run(d, L):
+    """g ramps 0 -> 40 with dt = 0.05: the link angle crosses pi/4, so the rotation form
+    switches from tan to cot in the middle of a chain of merged steps."""
+    ol = oracle.Lattice(d, L)
+    n, T = 20, 1.0
+    with gpu_ctx(d, L, C128) as ctx:
+        s = lgt.make_schedule(T, n, ramp=lgt.LGT_RAMP_COUPLING, g0=0.0, g1=40.0)
+        lgt.lgt_evolve(ctx, s, SYM, lgt.LGT_FORM_FUSED, 0, n)
+        got = get_state(ctx)
+    dt, cx, cz = oracle.schedule_coupling_ramp(T, n, 0.0, 40.0)
+    assert np.any(np.abs(np.tan(dt * np.asarray(cx))) > 1) and abs(np.tan(dt * cx[0])) < 1
+    want = oracle.evolve(oracle.plus_state(ol.N), ol, dt, cx, cz, 2)
+    assert np.max(np.abs(got - want)) < 1e-10
+
+
+def test_batch_with_mixed_forms_equals_single_runs():
+    """A batch whose instances use the tan form, the cot form, and both in turn."""
+    d, L, n, T = 2, (2, 4), 20, 1.0
+    scheds = [lgt.make_schedule(T, n, 1.0, 1.0), lgt.make_schedule(T, n, 25.0, 1.0),
+              lgt.make_schedule(T, n, ramp=lgt.LGT_RAMP_COUPLING, g0=0.0, g1=40.0)]
+    ctxs = [lgt.lgt_create(d, list(L), 1, C128) for _ in scheds]
+    try:
+        lgt.lgt_batch_evolve(ctxs, scheds, [SYM] * len(scheds), 0, n)
+        batched = [get_state(c) for c in ctxs]
+    finally:
+        for c in ctxs:
+            lgt.lgt_destroy(c)
+    for s, psi in zip(scheds, batched):
+        with gpu_ctx(d, L, C128) as ctx:
+            lgt.lgt_evolve(ctx, s, SYM, lgt.LGT_FORM_FUSED, 0, n)
+            assert np.array_equal(get_state(ctx), psi)
