@@ -17,6 +17,9 @@ SOURCES = ["kernels.hip", "api.cpp", "lattice.cpp", "schedule.cpp", "server.cpp"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",
           # packed FP32 instructions stay off: plain scalar FP32 is generated instead
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # multiply-adds fuse only within one expression, so every inlined copy of a
+          # kernel body rounds the same way (batched runs match single runs bit for bit)
+          "-ffp-contract=on",
           "-I", os.path.join(HERE, "..", "include")]
 
 

@@ -241,17 +241,10 @@ __global__ __launch_bounds__(kLowThreads) void k_low(const DevInst *__restrict__
 // persistent tile pass.  A workgroup of 2^W waves owns tiles of 2^(10+W) amplitudes
 // and walks over the tiles of its instance with a stride of gridDim.x, loading the
 // next tile into registers while it works on the current one.
-//
-// Layout A (load):  tile bit 0..5 = lane, 6..5+W = wave, 6+W..9+W = register.
-// Layout B (store): tile bit 0..5 = lane, 6..5+W = low W register bits,
-//                   6+W..5+2W = wave, 6+2W..9+W = high 4-W register bits.
-// Lanes always sit on the lowest tile bits, so every LDS access is a run of 64
-// consecutive slots (no bank conflicts) and every global access is coalesced.
-// Rotations: register bits in registers, lane bits across lanes (DPP within a row
-// of 16, shuffles for 16 and 32), wave bits in registers after one LDS exchange.
 //   low tile:  tile bit i = index bit i, all 10+W bits rotated.
-//   high tile: tile bits 0..CB-1 = index bits 0..CB-1 (rows of 128 bytes, not
+//   high tile: tile bits 0..CB-1 = index bits 0..CB-1 (rows of 2^CB amplitudes, not
 //              rotated), tile bit i >= CB = index bit hb + i - CB (rotated).
+// Layouts and the exchange between them are described at k_tile.
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x)
@@ -351,97 +344,178 @@ __device__ __forceinline__ void rot_lanes(C *v, T t)
 
 template <typename T, int W, int ROWB>
 struct PassGeom {
-    using C = cplx_t<T>;
     static constexpr bool LOW = ROWB >= 10 + W;
-    static constexpr int NT = 64 << W;
     static constexpr int TB = 10 + W;                        // tile bits
     static constexpr int CB = LOW ? TB : ROWB;               // contiguous row bits
-    static constexpr int LMASK = LOW ? 63 : (63 & ~((1 << CB) - 1));
-    static constexpr int MW = (1 << W) - 1;
-    // tile offsets of register r for a thread with lane l and wave w
-    static __device__ __forceinline__ int offA(int lw, int r) { return lw | (r << (6 + W)); }
-    static __device__ __forceinline__ int offB(int l, int w, int r)
+};
+
+// ---------------------------------------------------------------------------
+// Tile pass k_tile.  Each tile goes through two register layouts and back:
+//   layout A (load and store): tile bit 0..5 = lane, 6..5+W = wave, 6+W..9+W = register;
+//   layout B (after one LDS exchange): chosen so that every rotated bit is a register
+//   bit or one of the lane bits 0..3 (DPP within a row of 16) in A or in B.
+// A rotates its register bits and its lane bits 0..3; B rotates A's wave bits and tile
+// bits 4, 5 (in registers, at most two on DPP lanes).  The phase is applied in B, then
+// the tile goes back to A for the store.  A merged launch (MERGE) also applies the
+// next step's rotations after the phase: first B's, then A's, so every bit is rotated
+// once per step and in the same order in every kind of launch.  No bit needs a lane
+// exchange across rows.  In each exchange a thread writes exactly the LDS slots it read
+// in the previous one, so only the barrier between a write and the matching read is
+// needed (two per tile).  An XOR of tile bits 4, 5 into slot bits 2, 3 keeps every LDS
+// access of 16 lanes on 16 distinct consecutive slots.
+// ---------------------------------------------------------------------------
+struct MergeLayout {
+    int lane[6], wave[4], reg[4];   // tile bit of each B lane, wave and register index bit
+    int br1;                        // B register bits rotated before the phase
+    int bl;                         // B lane bits rotated across lanes (both rounds)
+    int al;                         // A lane bits rotated across lanes (both rounds)
+    int ar2;                        // A register bits rotated after the phase
+    int n_swz, swz_src[2], swz_dst[2];
+};
+
+constexpr MergeLayout merge_layout(int W, int TB, int CB)
+{
+    MergeLayout m{};
+    bool used[16] = {};
+    int need[6] = {}, nn = 0;
+    for (int k = 0; k < W; ++k) need[nn++] = 6 + k;          // A's wave bits
+    for (int b = 5; b >= 4; --b)
+        if (b >= CB) need[nn++] = b;                          // rotated lane bits 4, 5
+    int nr = 0;
+    for (int i = 0; i < nn && nr < 4; ++i) {
+        m.reg[nr++] = need[i];
+        used[need[i]] = true;
+    }
+    m.br1 = (1 << nr) - 1;
+    for (int k = 0; nr < 4; ++k) {                            // fillers: A register bits
+        m.reg[nr++] = 6 + W + k;
+        used[6 + W + k] = true;
+    }
+    int nl = 0;
+    for (int i = 4; i < nn; ++i) {                            // the rest of `need` on DPP lanes
+        m.lane[nl++] = need[i];
+        used[need[i]] = true;
+    }
+    m.bl = (1 << nl) - 1;
+    for (int b = 0; b < TB && nl < 6; ++b)
+        if (!used[b]) {
+            m.lane[nl++] = b;
+            used[b] = true;
+        }
+    int nw = 0;
+    for (int b = 0; b < TB; ++b)
+        if (!used[b]) m.wave[nw++] = b;
+    m.al = 0;
+    for (int k = CB; k < 4; ++k) m.al |= 1 << k;
+    m.ar2 = 15;
+    for (int k = 0; k < 4; ++k)
+        if (m.reg[k] >= 6 + W) m.ar2 &= ~(1 << (m.reg[k] - 6 - W));
+    // tile bits >= 4 on B lanes 0..3 pair with the bits of 0..3 missing there
+    bool in_lo[4] = {};
+    int ext[4] = {}, ne = 0;
+    for (int k = 0; k < 4; ++k) {
+        if (m.lane[k] < 4) in_lo[m.lane[k]] = true;
+        else ext[ne++] = m.lane[k];
+    }
+    for (int b = 0, i = 0; b < 4 && i < ne; ++b)
+        if (!in_lo[b]) {
+            m.swz_src[i] = ext[i];
+            m.swz_dst[i] = b;
+            ++i;
+            m.n_swz = i;
+        }
+    return m;
+}
+
+template <typename T, int W, int ROWB>
+struct MergeGeom {
+    using PG = PassGeom<T, W, ROWB>;
+    static constexpr int TB = PG::TB, CB = PG::CB;
+    static constexpr MergeLayout M = merge_layout(W, TB, PG::LOW ? 0 : CB);
+    // tile offset of B register index r
+    static constexpr int regB(int r)
     {
-        return l | ((r & MW) << 6) | (w << (6 + W)) | ((r >> W) << (6 + 2 * W));
+        int o = 0;
+        for (int k = 0; k < 4; ++k)
+            if (r & (1 << k)) o |= 1 << M.reg[k];
+        return o;
+    }
+    static constexpr int swz(int o)
+    {
+        for (int i = 0; i < M.n_swz; ++i) o ^= ((o >> M.swz_src[i]) & 1) << M.swz_dst[i];
+        return o;
+    }
+    static __device__ __forceinline__ int thrB(int l, int w)
+    {
+        int o = 0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) o |= ((l >> k) & 1) << M.lane[k];
+#pragma unroll
+        for (int k = 0; k < W; ++k) o |= ((w >> k) & 1) << M.wave[k];
+        return o;
     }
 };
 
-// TAN / TN: rotation form of step and step + 1.  MERGE: the launch also applies the next
-// step's rotation of the same tile bits after the phase (consecutive steps whose passes run
-// in opposite directions share this pass).  An instance whose last step is `step` stops
-// after the phase; it runs in the launch with TN == TAN.
+// TAN / TN: rotation form of step and step + 1.  MERGE: rotation of `step`, the phase
+// `post`, the rotation of step + 1; an instance whose last step is `step` stops after the
+// phase and runs in the launch with TN == TAN.  Otherwise: the phase `pre` (if >= 0),
+// the rotation of `step`, the phase `post` (if >= 0).
 template <typename T, int W, int ROWB, bool TAN, bool TN, bool MERGE>
-__global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ insts, int n, int hb,
+__global__ __launch_bounds__(64 << W) void k_tile(const DevInst *__restrict__ insts, int n, int hb,
                                                   int step, int pre, int post, int n_plaq)
 {
     using C = cplx_t<T>;
     using G = PassGeom<T, W, ROWB>;
+    using MG = MergeGeom<T, W, ROWB>;
     constexpr bool LOW = G::LOW;
     constexpr int TB = G::TB, CB = G::CB;
-    __shared__ C buf[W > 0 ? (1 << TB) : 1];
+    constexpr MergeLayout M = MG::M;
+    static_assert(MG::swz(0) == 0, "layout");
+    __shared__ C buf[1 << TB];
     __shared__ uint32_t ptab[kPtabWords];
-    __shared__ C ph_pre[kMaxPlaq + 1], ph_post[kMaxPlaq + 1];
+    __shared__ C ph_pre[MERGE ? 1 : kMaxPlaq + 1], ph_post[kMaxPlaq + 1];
+    static_assert(MERGE || TN == TAN, "single-step passes have one form");
 
     const DevInst in = insts[blockIdx.y];
     if (in.step0 + step >= in.n_total) return;   // instance already finished (uniform per block)
     const gp<const RotParam<T>> rot = (gp<const RotParam<T>>)in.rot;
     const RotParam<T> rp = ldg(rot + (in.step0 + step));
-    if ((rp.u == T(1)) != TAN) return;           // the other rotation form has its own launch
-    const gp<C> psi = (gp<C>)in.psi;
+    if ((rp.u == T(1)) != TAN) return;           // the other form pairs have their own launches
     const T tt = TAN ? rp.v : rp.u;
     T tn = tt;
-    bool more = false;                           // merged and the instance has step + 1
-    if constexpr (MERGE) {
-        more = in.step0 + step + 1 < in.n_total;
-        if (more) {
-            const RotParam<T> rq = ldg(rot + (in.step0 + step + 1));
-            if ((rq.u == T(1)) != TN) return;
-            tn = TN ? rq.v : rq.u;
-        } else if (TN != TAN) {
-            return;
-        }
-    } else {
-        static_assert(MERGE || TN == TAN, "single-step passes have one form");
+    // merged and the instance has step + 1; else the pass stops after the phase
+    const bool more = MERGE && in.step0 + step + 1 < in.n_total;
+    if (more) {
+        const RotParam<T> rq = ldg(rot + (in.step0 + step + 1));
+        if ((rq.u == T(1)) != TN) return;
+        tn = TN ? rq.v : rq.u;
+    } else if (TN != TAN) {
+        return;
     }
+    const gp<C> psi = (gp<C>)in.psi;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t n_tiles = 1ull << (n - TB);
     const int lowb = LOW ? 0 : hb - CB;
-    // element offset of a tile's first amplitude
     auto tile_base = [&](uint64_t tile) -> uint64_t {
         if constexpr (LOW) return tile << TB;
         else return ((tile & ((1ull << lowb) - 1)) << CB) | ((tile >> lowb) << (hb + TB - CB));
     };
-    // offset of tile offset o inside a tile (tile bits >= CB spread from index bit hb)
     auto spread = [&](int o) -> uint64_t {
         if constexpr (LOW) return (uint64_t)o;
         else return (uint64_t)(o & ((1 << CB) - 1)) | ((uint64_t)(o >> CB) << hb);
     };
     auto gbit = [&](int i) -> int { return (LOW || i < CB) ? i : hb + (i - CB); };
-    const int lwA = l | (w << 6);
-    const int lwB = l | (w << (6 + W));
-    // per-thread element offsets fit 32 bits (checked by the launcher)
-    const uint32_t thrA = (uint32_t)spread(lwA), thrB = (uint32_t)spread(lwB);
-    auto load = [&](uint64_t tile, C *dst) {
-        const gp<const C> tp = psi + tile_base(tile);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) dst[r] = ldg(tp + spread(r << (6 + W)) + thrA);
-    };
-    // Prefetch of the tile after `tile` when there is one; otherwise 16 loads of the
-    // tile's first row (cached, values unused), so that every tile is worked on with the
-    // same number of memory operations in flight and the wait before it only covers its
-    // own loads, not the previous tile's stores.
-    auto prefetch = [&](uint64_t tile, uint64_t next, C *dst) {
-        const bool real = next < n_tiles;
-        const gp<const C> tp = psi + tile_base(real ? next : tile);
-        const uint32_t lo = real ? thrA : (uint32_t)l;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) dst[r] = ldg(tp + (real ? spread(r << (6 + W)) : 0) + lo);
-    };
+    const int oA = l | (w << 6), oB = MG::thrB(l, w);
+    const int sA = MG::swz(oA), sB = MG::swz(oB);   // LDS slots of register 0
+    const uint32_t thrA = (uint32_t)spread(oA), thrBg = (uint32_t)spread(oB);
     uint64_t tile = blockIdx.x;
     if (tile >= n_tiles) return;
     C v[16], nv[16];
-    load(tile, v);   // first tile in flight while the tables are staged
-    // tables are only needed by passes that apply a phase
+    {
+        const gp<const C> tp = psi + tile_base(tile);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = ldg(tp + spread(r << (6 + W)) + thrA);
+    }
     const bool phased = MERGE || pre >= 0 || post >= 0;
     uint32_t pra[16], prb[16];
     if (phased) {
@@ -451,58 +525,50 @@ __global__ __launch_bounds__(64 << W) void k_pass(const DevInst *__restrict__ in
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             qa[k] = link_set(gbit(6 + W + k), ptab);
-            qb[k] = link_set(gbit(k < W ? 6 + k : 6 + W + k), ptab);
+            qb[k] = link_set(gbit(M.reg[k]), ptab);
         }
         reg_sets(qa, pra);
         reg_sets(qb, prb);
     }
-
-    // one tile: rotations, the exchange, the phase, the store (merged: the next step's
-    // rotations after the phase, and a second exchange back to the load layout)
-    auto work = [&](uint64_t t_id, C *x) __attribute__((always_inline)) {
-        const gp<C> tp = psi + tile_base(t_id);
-        if (!MERGE && pre >= 0)
-            apply_phase_pr<C>(x, syndrome(tile_base(t_id) + thrA, ptab), pra, ph_pre);
-        rot_regs_s<TAN, 15, T, C>(x, tt);
-        rot_lanes<TAN, G::LMASK, T, C>(x, tt);
-        if constexpr (W > 0) {
+    auto prefetch = [&](uint64_t cur, uint64_t next, C *dst) {
+        const bool real = next < n_tiles;
+        const gp<const C> tp = psi + tile_base(real ? next : cur);
+        const uint32_t lo = real ? thrA : (uint32_t)l;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) buf[G::offA(lwA, r)] = x[r];
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < 16; ++r) x[r] = buf[G::offB(l, w, r)];
-            __syncthreads();
-            rot_regs_s<TAN, (1 << W) - 1, T, C>(x, tt);
-        }
-        if (MERGE || post >= 0)
-            apply_phase_pr<C>(x, syndrome(tile_base(t_id) + (W > 0 ? thrB : thrA), ptab),
-                              W > 0 ? prb : pra, ph_post);
-        if (MERGE && more) {
-            // layout B holds every tile bit but its wave bits in registers or lanes
-            rot_regs_s<TN, 15, T, C>(x, tn);
-            rot_lanes<TN, G::LMASK, T, C>(x, tn);
-            if constexpr (W > 0) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) buf[G::offB(l, w, r)] = x[r];
-                __syncthreads();
-#pragma unroll
-                for (int r = 0; r < 16; ++r) x[r] = buf[G::offA(lwA, r)];
-                __syncthreads();
-                rot_regs_s<TN, (1 << W) - 1, T, C>(x, tn);
-            }
-#pragma unroll
-            for (int r = 0; r < 16; ++r) stg(tp + spread(r << (6 + W)) + thrA, x[r]);
-        } else {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                if constexpr (W > 0) stg(tp + spread(G::offB(0, 0, r)) + thrB, x[r]);
-                else stg(tp + spread(r << (6 + W)) + thrA, x[r]);
-            }
-        }
+        for (int r = 0; r < 16; ++r) dst[r] = ldg(tp + (real ? spread(r << (6 + W)) : 0) + lo);
     };
-    // two register buffers alternate: while one tile is worked on, the next one loads.
-    // The first tile is peeled so that every work in the loop follows the same sequence
-    // (own loads, previous stores, next loads) on every path.
+    auto work = [&](uint64_t t_id, C *x) __attribute__((always_inline)) {
+        const uint64_t base = tile_base(t_id);
+        if (!MERGE && pre >= 0) apply_phase_pr<C>(x, syndrome(base + thrA, ptab), pra, ph_pre);
+        // before the phase: A registers and lanes 0..3
+        rot_regs_s<TAN, 15, T, C>(x, tt);
+        rot_lanes<TAN, M.al, T, C>(x, tt);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[sA + (r << (6 + W))] = x[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = buf[sB + MG::regB(r)];
+        // before the phase: B registers and lanes holding A's wave bits and bits 4, 5
+        rot_regs_s<TAN, M.br1, T, C>(x, tt);
+        rot_lanes<TAN, M.bl, T, C>(x, tt);
+        if (MERGE || post >= 0) apply_phase_pr<C>(x, syndrome(base + thrBg, ptab), prb, ph_post);
+        if (more) {
+            rot_regs_s<TN, 15, T, C>(x, tn);
+            rot_lanes<TN, M.bl, T, C>(x, tn);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[sB + MG::regB(r)] = x[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = buf[sA + (r << (6 + W))];
+        if (more) {
+            rot_regs_s<TN, M.ar2, T, C>(x, tn);
+            rot_lanes<TN, M.al, T, C>(x, tn);
+        }
+        const gp<C> tp = psi + base;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) stg(tp + spread(r << (6 + W)) + thrA, x[r]);
+    };
     uint64_t next = tile + gridDim.x;
     prefetch(tile, next, nv);
     work(tile, v);
@@ -1041,21 +1107,21 @@ static hipError_t launch_pass_t(const DevInst *dev_inst, int n_inst, int n, int 
         if (pre >= 0 || post < 0) return hipErrorInvalidValue;   // merged: one phase between
         const int fa = forms & 3, fb = (forms >> 2) & 3;
         if (fa & 1) {
-            hipLaunchKernelGGL((k_pass<T, W, ROWB, true, true, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+            hipLaunchKernelGGL((k_tile<T, W, ROWB, true, true, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
             if (fb & 2)
-                hipLaunchKernelGGL((k_pass<T, W, ROWB, true, false, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+                hipLaunchKernelGGL((k_tile<T, W, ROWB, true, false, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
         }
         if (fa & 2) {
-            hipLaunchKernelGGL((k_pass<T, W, ROWB, false, false, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+            hipLaunchKernelGGL((k_tile<T, W, ROWB, false, false, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
             if (fb & 1)
-                hipLaunchKernelGGL((k_pass<T, W, ROWB, false, true, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+                hipLaunchKernelGGL((k_tile<T, W, ROWB, false, true, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
         }
         return hipGetLastError();
     }
     if (forms & 1)
-        hipLaunchKernelGGL((k_pass<T, W, ROWB, true, true, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
+        hipLaunchKernelGGL((k_tile<T, W, ROWB, true, true, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
     if (forms & 2)
-        hipLaunchKernelGGL((k_pass<T, W, ROWB, false, false, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
+        hipLaunchKernelGGL((k_tile<T, W, ROWB, false, false, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
     return hipGetLastError();
 }
 
