@@ -189,9 +189,10 @@ def variants(lgt):
     """Per-Trotter-step time of the other precisions, forms and sizes (secondary)."""
     out = {}
 
-    def per_step(d, L, dtype, n, form=0, order=2):
+    def per_step(d, L, dtype, n, form=0, order=2, plan=0):
         ctx = lgt.lgt_create(d, list(L), 1, dtype)
         try:
+            lgt.lgt_set_plan(ctx, plan)
             s = lgt.make_schedule(0.05 * n, n, 1.0, 1.0)
             lgt.lgt_evolve(ctx, s, order, form, 0, min(n, 2))
             lgt.lgt_sync(ctx)
@@ -206,6 +207,11 @@ def variants(lgt):
                 "algorithmic_GBps": 2 * sb / el / 1e9,
                 "algorithmic_hbm_frac": 2 * sb / el / 1e9 / HBM_PEAK_GBS}
 
+    # the same workload without merged steps (one launch per pass and step)
+    out["2x2x2_c64_fused_unmerged"] = per_step(3, (2, 2, 2), lgt.LGT_C64, 200,
+                                               plan=lgt.LGT_PLAN_NO_MERGE)
+    # 28 links (2 GiB): larger than the 256 MB Infinity Cache, so the passes stream HBM
+    out["2x7_c64_fused_28links"] = per_step(2, (2, 7), lgt.LGT_C64, 40)
     out["2x2x2_c128_fused"] = per_step(3, (2, 2, 2), lgt.LGT_C128, 200)
     out["2x2x2_c64_circuit"] = per_step(3, (2, 2, 2), lgt.LGT_C64, 4, form=1)
     out["2x2x2_c128_circuit"] = per_step(3, (2, 2, 2), lgt.LGT_C128, 2, form=1)
