@@ -224,7 +224,16 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
     (void)n_inst;
     const bool merge = !(plan & kPlanNoMerge);
     plan &= ~kPlanNoMerge;
-    if (plan == 0) plan = (n_links >= big && (1 << (n_links - big)) >= 64) ? 2 : 1;
+    if (plan == 0) {
+        // big low tiles when they give at least 64 workgroups and need no register pass
+        plan = (n_links >= big && (1 << (n_links - big)) >= 64) ? 2 : 1;
+        if (plan == 2) {
+            const PassPlan p2 = plan_passes(n_links, dtype, 2 | (merge ? 0 : kPlanNoMerge), n_inst);
+            for (int i = 0; i < p2.n_passes; ++i)
+                if (p2.pass[i].kind == PASS_HIGH_REG) plan = 1;
+            if (plan == 2) return p2;
+        }
+    }
     if (plan == 4) {
         // the 12-bit LDS tile with 256 threads followed by register passes of <= 6 bits
         p.pass[p.n_passes++] = Pass{PASS_LOW12, 0, 12, 0};
