@@ -278,9 +278,47 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 
 // a <- u a + i v a_partner for every register, partner across lane bit B.  tv / ntv hold
 // t and -t in vector registers, so the cross-lane move can fold into the multiply-add.
+// acc + src[partner lane] * mul, the lane permutation applied to src inside the multiply-
+// add (DPP operand of v_fmac_f32).  The s_nop gives the two wait states a DPP read needs
+// after a vector write of its source register.
+template <int B>
+__device__ __forceinline__ float fmac_partner(float acc, float src, float mul)
+{
+    if constexpr (B == 0)
+        asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
+            : "+v"(acc) : "v"(src), "v"(mul));
+    else if constexpr (B == 1)
+        asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
+            : "+v"(acc) : "v"(src), "v"(mul));
+    else if constexpr (B == 2)   // src already half-row mirrored: lane ^ 4 = mirror then ^ 3
+        asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[3,2,1,0] row_mask:0xf bank_mask:0xf"
+            : "+v"(acc) : "v"(src), "v"(mul));
+    else
+        asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:8 row_mask:0xf bank_mask:0xf"
+            : "+v"(acc) : "v"(src), "v"(mul));
+    return acc;
+}
+
 template <int B, bool TAN, typename T, typename C>
 __device__ __forceinline__ void rot_lane(C *v, T tv, T ntv)
 {
+    if constexpr (TAN && sizeof(T) == 4 && B < 4) {
+        // x' = x - t y[partner], y' = y + t x[partner]: one permutation rides in a
+        // multiply-add, the other (of the value the first one overwrites) is a move
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if constexpr (B == 2) {
+                const T mx = dpp_f<0x141>(v[r].x), my = dpp_f<0x141>(v[r].y);
+                v[r].x = fmac_partner<2>(v[r].x, my, ntv);
+                v[r].y = fmac_partner<2>(v[r].y, mx, tv);
+            } else {
+                const T pi = lane_partner<B>(v[r].y);
+                v[r].y = fmac_partner<B>(v[r].y, v[r].x, tv);
+                v[r].x = fma_t(ntv, pi, v[r].x);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const T pr = lane_partner<B>(v[r].x), pi = lane_partner<B>(v[r].y);
@@ -530,28 +568,36 @@ __global__ __launch_bounds__(64 << W) void k_tile(const DevInst *__restrict__ in
         reg_sets(qa, pra);
         reg_sets(qb, prb);
     }
-    auto prefetch = [&](uint64_t cur, uint64_t next, C *dst) {
-        const bool real = next < n_tiles;
-        const gp<const C> tp = psi + tile_base(real ? next : cur);
-        const uint32_t lo = real ? thrA : (uint32_t)l;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) dst[r] = ldg(tp + (real ? spread(r << (6 + W)) : 0) + lo);
-    };
-    auto work = [&](uint64_t t_id, C *x) __attribute__((always_inline)) {
+    // One tile.  The next tile (or, without one, 16 cached loads of this tile's first row,
+    // so that every tile sees the same memory operations in flight) is loaded into `y` in
+    // four groups of registers spread over the work: loads issued in one burst stall the
+    // issuing waves once the memory queues are full, and the vector units idle meanwhile.
+    auto work = [&](uint64_t t_id, C *x, C *y, uint64_t nxt) __attribute__((always_inline)) {
         const uint64_t base = tile_base(t_id);
+        const bool real = nxt < n_tiles;
+        const gp<const C> tq = psi + tile_base(real ? nxt : t_id);
+        const uint32_t lo = real ? thrA : (uint32_t)l;
+        auto fetch = [&](int g) __attribute__((always_inline)) {
+#pragma unroll
+            for (int r = 4 * g; r < 4 * g + 4; ++r)
+                y[r] = ldg(tq + (real ? spread(r << (6 + W)) : 0) + lo);
+        };
+        fetch(0);
         if (!MERGE && pre >= 0) apply_phase_pr<C>(x, syndrome(base + thrA, ptab), pra, ph_pre);
-        // before the phase: A registers and lanes 0..3
-        rot_regs_s<TAN, 15, T, C>(x, tt);
+        // before the phase: A lanes 0..3 (register by register) and A registers
         rot_lanes<TAN, M.al, T, C>(x, tt);
+        rot_regs_s<TAN, 15, T, C>(x, tt);
 #pragma unroll
         for (int r = 0; r < 16; ++r) buf[sA + (r << (6 + W))] = x[r];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = buf[sB + MG::regB(r)];
+        fetch(1);
         // before the phase: B registers and lanes holding A's wave bits and bits 4, 5
         rot_regs_s<TAN, M.br1, T, C>(x, tt);
         rot_lanes<TAN, M.bl, T, C>(x, tt);
         if (MERGE || post >= 0) apply_phase_pr<C>(x, syndrome(base + thrBg, ptab), prb, ph_post);
+        fetch(2);
         if (more) {
             rot_regs_s<TN, 15, T, C>(x, tn);
             rot_lanes<TN, M.bl, T, C>(x, tn);
@@ -561,6 +607,7 @@ __global__ __launch_bounds__(64 << W) void k_tile(const DevInst *__restrict__ in
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = buf[sA + (r << (6 + W))];
+        fetch(3);
         if (more) {
             rot_regs_s<TN, M.ar2, T, C>(x, tn);
             rot_lanes<TN, M.al, T, C>(x, tn);
@@ -569,19 +616,18 @@ __global__ __launch_bounds__(64 << W) void k_tile(const DevInst *__restrict__ in
 #pragma unroll
         for (int r = 0; r < 16; ++r) stg(tp + spread(r << (6 + W)) + thrA, x[r]);
     };
+    // two register buffers alternate.  The first tile is peeled so that every tile in the
+    // loop follows the same sequence of memory operations on every path.
     uint64_t next = tile + gridDim.x;
-    prefetch(tile, next, nv);
-    work(tile, v);
+    work(tile, v, nv, next);
     while (next < n_tiles) {
         tile = next;
         next = tile + gridDim.x;
-        prefetch(tile, next, v);
-        work(tile, nv);
+        work(tile, nv, v, next);
         if (next >= n_tiles) break;
         tile = next;
         next = tile + gridDim.x;
-        prefetch(tile, next, nv);
-        work(tile, v);
+        work(tile, v, nv, next);
     }
 }
 
