@@ -211,6 +211,43 @@ typedef struct {
 lgt_status lgt_measure(lgt_ctx *ctx, const lgt_observable *obs, double *out, size_t out_len);
 
 /*
+ * lgt_scan: the stepwise adiabatic evolution of Sec. 2.2, paused for measurement after every
+ * `substeps` substeps (one "step" of the paper is n substeps of length t_s/n; Sec. 3 computes
+ * its quantities after each step).  Runs substeps * n_points substeps of `sched` from
+ * first_step in the fused form, each block as one lgt_evolve call (the symmetric half phases
+ * close at every pause), and writes after block k, in row k of `out` (row-major,
+ * n_points rows of 5 + n_masks doubles):
+ *   [0], [1]  cx and cz of the block's last substep (cx is the coupling g of the paper form)
+ *   [2]       <Z> = sum_p <Z_p> = -sum_p <U_p>            (Sec. 2.1: Z_p = -prod sigma^z)
+ *   [3]       <X> = -sum_l <sigma^x_l>, so <H> = cz <Z> + cx <X>   (Sec. 3.2)
+ *   [4]       the norm <psi|psi>
+ *   [5 + i]   <prod_{l in masks[i]} sigma^z_l>, Wegner-Wilson loops (Sec. 3.1)
+ * Expectations are divided by the norm.  Every measurement is an FP64 reduction on the
+ * device, queued behind the evolution without host round trips; the call returns when the
+ * last row is on the host.  0 <= n_masks <= 32; masks must not have bits at or beyond N_l.
+ * E_INVALID for bad counts, masks, a short `out` or a schedule range outside the schedule.
+ */
+lgt_status lgt_scan(lgt_ctx *ctx, const lgt_schedule *sched, lgt_order order,
+                    int64_t first_step, int64_t substeps, int64_t n_points,
+                    const uint64_t *masks, int n_masks, double *out, size_t out_len);
+
+/*
+ * Host-side analysis of a scan (no device work; ctx not needed).
+ * lgt_critical_point: Sec. 3.2 locates g_c at the lowest point of the valley of
+ *   d^2<H>/dg^2.  The second derivative is the three-point difference over neighbours
+ *   `stride` points apart (stride >= 1 smooths the per-step curve), its minimum is refined
+ *   by the parabola through the lowest point and its two neighbours.  g: n increasing
+ *   couplings, h: <H> at each; *g_c receives the minimum's position, *d2_min its value.
+ *   E_INVALID if n < 2 * stride + 3 or g is not increasing.
+ * lgt_crossing: the first coupling where a - b changes sign (Sec. 3.2: <Z> and <X> cross
+ *   at the self-dual point of the 3+1D theory), by linear interpolation between the two
+ *   bracketing points.  E_INVALID if there is no sign change.
+ */
+lgt_status lgt_critical_point(const double *g, const double *h, int n, int stride,
+                              double *g_c, double *d2_min);
+lgt_status lgt_crossing(const double *g, const double *a, const double *b, int n, double *g_x);
+
+/*
  * lgt_sample: n_shots computational-basis samples written to the host array
  * out (bit q of out[i] = link q).  Shot i draws u_i from the counter-based
  * SplitMix64 stream (finaliser of seed + (i+1)*0x9E3779B97F4A7C15, top 53

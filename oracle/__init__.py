@@ -322,6 +322,33 @@ def cdf(psi, N) -> np.ndarray:
     return out
 
 
+def adiabatic_scan(lat: Lattice, psi0: np.ndarray, g_f: float, n_points: int, substeps: int,
+                   t_s: float, order: int, loops=()) -> np.ndarray:
+    """The stepwise adiabatic evolution of Sec. 2.2 with a pause after every step.
+
+    H_{k,m} = Z + g_{k,m} X with g_{k,m} = (k-1) g_s + m delta, g_s = g_f / N_s and
+    delta = g_s / n: step k is n substeps of length t_s / n, each a first-order (eq. (a))
+    or symmetric (eq. (s)) Trotter factor.  After every step the evolution pauses and
+    <Z> = -sum_p <U_p>, <X> = -sum_l <sigma^x_l>, the norm and the Wegner-Wilson loops
+    <prod_{l in loop} sigma^z_l> are computed (Sec. 3).  Rows: (g, 1, <Z>, <X>, norm,
+    loops...), expectations divided by the norm.
+    """
+    N = lat.N
+    total = n_points * substeps
+    dt, cx, cz = schedule_coupling_ramp(t_s * n_points, total, 0.0, g_f)
+    psi = np.array(psi0, dtype=np.complex128)
+    rows = []
+    for k in range(n_points):
+        sl = slice(k * substeps, (k + 1) * substeps)
+        psi = evolve(psi, lat, dt, cx[sl], cz[sl], order)
+        n2 = norm2(psi, N)
+        z = -sum(raw_z(psi, N, p) for p in lat.plaq) / n2
+        x = -sum(raw_x(psi, N, [q]) for q in range(N)) / n2
+        w = [raw_z(psi, N, list(loop)) / n2 for loop in loops]
+        rows.append([cx[sl][-1], cz[sl][-1], z, x, n2] + w)
+    return np.array(rows)
+
+
 def zground_state(lat: Lattice) -> np.ndarray:
     """prod_p P_p |+>^N normalised, P_p = (1 + U_p)/2 projecting on Z_p = -1 (Sec. 2.3)."""
     N = lat.N

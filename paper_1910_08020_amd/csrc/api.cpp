@@ -576,6 +576,9 @@ lgt_status lgt_reset(lgt_ctx *c, lgt_init init, uint64_t basis_index)
     return LGT_OK;
 }
 
+static lgt_status evolve_fused(lgt_ctx *c, double dt, const std::vector<double> &cx,
+                               const std::vector<double> &cz, lgt_order order);
+
 lgt_status lgt_evolve(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, lgt_form form,
                       int64_t first_step, int64_t count)
 {
@@ -632,7 +635,17 @@ lgt_status lgt_evolve(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, lg
         }
         return LGT_OK;
     }
+    return evolve_fused(c, dt, cx, cz, order);
+}
+
+// fused form: the whole call as one chain of pass launches (tables staged once)
+static lgt_status evolve_fused(lgt_ctx *c, double dt, const std::vector<double> &cx,
+                               const std::vector<double> &cz, lgt_order order)
+{
+    const Lattice &lat = c->lat;
+    const int64_t count = (int64_t)cx.size();
     if (count > (1 << 24)) return fail(c, LGT_E_INVALID, "too many steps in one call");
+    StepTables st;
     Tables tb;
     make_tables(lat, c->dtype, dt, cx, cz, order, st, tb);
     const size_t rb = align256(tb.rot_bytes), pb = align256(tb.ph_bytes);
@@ -776,6 +789,160 @@ lgt_status lgt_measure(lgt_ctx *c, const lgt_observable *obs, double *out, size_
     if ((s = reduce_masks(c, flip, masks.data(), (int)masks.size(), v))) return s;
     for (size_t i = 0; i < masks.size(); ++i) out[i] = (double)(v[i] / nrm);
     return LGT_OK;
+}
+
+lgt_status lgt_scan(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, int64_t first_step,
+                    int64_t substeps, int64_t n_points, const uint64_t *masks, int n_masks,
+                    double *out, size_t out_len)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (!sched || !out) return fail(c, LGT_E_INVALID, "null argument");
+    if (order != LGT_ORDER_TROTTER && order != LGT_ORDER_SYMMETRIC)
+        return fail(c, LGT_E_INVALID, "bad order");
+    if (substeps < 1 || n_points < 1 || n_masks < 0 || n_masks > 32 || (n_masks > 0 && !masks))
+        return fail(c, LGT_E_INVALID, "bad scan sizes");
+    const Lattice &lat = c->lat;
+    const int n = lat.n_links;
+    for (int i = 0; i < n_masks; ++i)
+        if (masks[i] >> n) return fail(c, LGT_E_INVALID, "mask has bits beyond N");
+    const int width = 5 + n_masks;
+    if (out_len < (size_t)n_points * width) return fail(c, LGT_E_INVALID, "output array too short");
+    // the whole range must lie inside the schedule
+    {
+        double dt0;
+        std::vector<double> a, b;
+        std::string why = schedule_coeffs(sched, first_step + substeps * (n_points - 1), substeps, dt0, a, b);
+        if (!why.empty()) return fail(c, LGT_E_INVALID, why);
+    }
+    // diagonal masks: the norm, the plaquettes, the loops; off-diagonal: single links
+    std::vector<uint64_t> mk(1, 0);
+    mk.insert(mk.end(), lat.plaq_mask.begin(), lat.plaq_mask.end());
+    mk.insert(mk.end(), masks, masks + n_masks);
+    const int nd = (int)mk.size();
+    for (int q = 0; q < n; ++q) mk.push_back(1ull << q);
+    const int ncol = (int)mk.size();
+    void *mdev = nullptr;
+    double *sums = nullptr;
+    auto cleanup = [&] {
+        if (mdev) (void)hipFree(mdev);
+        if (sums) (void)hipFree(sums);
+    };
+    auto bail = [&](lgt_status st, const std::string &m) {
+        (void)hipStreamSynchronize(c->stream);
+        cleanup();
+        return fail(c, st, m);
+    };
+    if (hipMalloc(&mdev, sizeof(uint64_t) * ncol) != hipSuccess ||
+        hipMalloc((void **)&sums, sizeof(double) * ncol * (size_t)n_points) != hipSuccess)
+        return bail(LGT_E_OOM, "scan buffers");
+    if (hipMemcpy(mdev, mk.data(), sizeof(uint64_t) * ncol, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(LGT_E_DEVICE, "scan mask upload");
+    const uint64_t *md = (const uint64_t *)mdev;
+    const int g = reduce_blocks(n);
+    std::vector<double> cxs(n_points), czs(n_points);
+    for (int64_t k = 0; k < n_points; ++k) {
+        double dt = 0;
+        std::vector<double> cx, cz;
+        std::string why = schedule_coeffs(sched, first_step + k * substeps, substeps, dt, cx, cz);
+        if (!why.empty()) return bail(LGT_E_INVALID, why);
+        cxs[k] = cx.back();
+        czs[k] = cz.back();
+        if ((s = evolve_fused(c, dt, cx, cz, order))) {
+            std::string m = c->err;
+            return bail(s, m);
+        }
+        double *row = sums + (size_t)k * ncol;
+        hipError_t e = hipSuccess;
+        for (int off = 0; off < nd && e == hipSuccess; off += kMaskChunk) {
+            const int m = std::min(kMaskChunk, nd - off);
+            e = timed(c, KF_RED_DIAG, [&] {
+                return launch_reduce_diag(c->dtype, c->state, n, md + off, m, c->partials, c->stream);
+            });
+            if (e == hipSuccess) e = launch_sum_cols(c->partials, g, kMaskChunk, m, row + off, c->stream);
+        }
+        for (int off = nd; off < ncol && e == hipSuccess; off += kFlipChunk) {
+            const int m = std::min(kFlipChunk, ncol - off);
+            e = timed(c, KF_RED_FLIP, [&] {
+                return launch_reduce_flip(c->dtype, c->state, n, md + off, m, c->partials, c->stream);
+            });
+            if (e == hipSuccess) e = launch_sum_cols(c->partials, g, kFlipChunk, m, row + off, c->stream);
+        }
+        if (e != hipSuccess) return bail(LGT_E_DEVICE, std::string("scan readout: ") + hipGetErrorString(e));
+    }
+    std::vector<double> host((size_t)ncol * n_points);
+    if (hipMemcpyAsync(host.data(), sums, sizeof(double) * host.size(), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return bail(LGT_E_DEVICE, "scan download");
+    cleanup();
+    for (int64_t k = 0; k < n_points; ++k) {
+        const double *h = &host[(size_t)k * ncol];
+        double *o = out + (size_t)k * width;
+        const long double nrm = h[0];
+        long double zs = 0, xs = 0;
+        for (int p = 0; p < lat.n_plaq; ++p) zs += h[1 + p];
+        for (int q = 0; q < n; ++q) xs += h[nd + q];
+        o[0] = cxs[k];
+        o[1] = czs[k];
+        o[2] = nrm > 0 ? (double)(-zs / nrm) : 0.0;
+        o[3] = nrm > 0 ? (double)(-xs / nrm) : 0.0;
+        o[4] = (double)nrm;
+        for (int i = 0; i < n_masks; ++i) o[5 + i] = nrm > 0 ? (double)(h[1 + lat.n_plaq + i] / nrm) : 0.0;
+    }
+    return LGT_OK;
+}
+
+lgt_status lgt_critical_point(const double *g, const double *h, int n, int stride,
+                              double *g_c, double *d2_min)
+{
+    if (!g || !h || !g_c || !d2_min || stride < 1 || n < 2 * stride + 3)
+        return fail(nullptr, LGT_E_INVALID, "critical point: bad arguments");
+    for (int i = 1; i < n; ++i)
+        if (!(g[i] > g[i - 1])) return fail(nullptr, LGT_E_INVALID, "couplings must increase");
+    std::vector<double> d2(n, 0.0);
+    int best = -1;
+    for (int i = stride; i + stride < n; ++i) {
+        const double gl = g[i - stride], gm = g[i], gr = g[i + stride];
+        d2[i] = 2.0 * ((h[i + stride] - h[i]) / (gr - gm) - (h[i] - h[i - stride]) / (gm - gl)) / (gr - gl);
+        if (best < 0 || d2[i] < d2[best]) best = i;
+    }
+    double x = g[best], y = d2[best];
+    if (best - 1 >= stride && best + 1 + stride < n) {
+        // vertex of the parabola through the lowest point and its neighbours
+        const double x0 = g[best - 1], x1 = g[best], x2 = g[best + 1];
+        const double y0 = d2[best - 1], y1 = d2[best], y2 = d2[best + 1];
+        const double den = (x0 - x1) * (x0 - x2) * (x1 - x2);
+        const double A = (x2 * (y1 - y0) + x1 * (y0 - y2) + x0 * (y2 - y1)) / den;
+        const double B = (x2 * x2 * (y0 - y1) + x1 * x1 * (y2 - y0) + x0 * x0 * (y1 - y2)) / den;
+        const double C = (x1 * x2 * (x1 - x2) * y0 + x2 * x0 * (x2 - x0) * y1 + x0 * x1 * (x0 - x1) * y2) / den;
+        if (A > 0) {
+            const double xv = -B / (2 * A);
+            if (xv >= x0 && xv <= x2) {
+                x = xv;
+                y = C - B * B / (4 * A);
+            }
+        }
+    }
+    *g_c = x;
+    *d2_min = y;
+    return LGT_OK;
+}
+
+lgt_status lgt_crossing(const double *g, const double *a, const double *b, int n, double *g_x)
+{
+    if (!g || !a || !b || !g_x || n < 2) return fail(nullptr, LGT_E_INVALID, "crossing: bad arguments");
+    for (int i = 1; i < n; ++i) {
+        const double d0 = a[i - 1] - b[i - 1], d1 = a[i] - b[i];
+        if (d0 == 0) {
+            *g_x = g[i - 1];
+            return LGT_OK;
+        }
+        if ((d0 < 0) != (d1 < 0) || d1 == 0) {
+            *g_x = g[i - 1] + (g[i] - g[i - 1]) * d0 / (d0 - d1);
+            return LGT_OK;
+        }
+    }
+    return fail(nullptr, LGT_E_INVALID, "no crossing");
 }
 
 lgt_status lgt_sample(lgt_ctx *c, uint64_t n_shots, uint64_t seed, uint64_t *out)

@@ -991,6 +991,17 @@ __global__ __launch_bounds__(kRedThreads) void k_red_flip(const cplx_t<T> *__res
     block_sum_store<kFlipMasks>(acc, partials + (size_t)blockIdx.x * kFlipMasks);
 }
 
+// out[c] = sum over rows of partials[row][c], c < ncols: one block per column, each thread
+// sums a fixed set of rows, then a fixed-order block sum (the same result every call)
+__global__ __launch_bounds__(kRedThreads) void k_sum_cols(const double *__restrict__ partials,
+                                                          int rows, int width, double *out)
+{
+    const int c = blockIdx.x;
+    double acc = 0;
+    for (int r = threadIdx.x; r < rows; r += kRedThreads) acc += partials[(size_t)r * width + c];
+    block_sum_store<1>(&acc, out + c);
+}
+
 // Z density of states: acc[m] += |psi_b|^2 for the m = popcount(P(b)) bin
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_red_dos(const cplx_t<T> *__restrict__ psi, int n,
@@ -1383,6 +1394,14 @@ hipError_t launch_reduce_dos(int dtype, const void *psi, int n, const uint32_t *
     else
         hipLaunchKernelGGL(k_red_dos<double>, dim3(g), dim3(kRedThreads), 0, st,
                            (const double2 *)psi, n, ptab_dev, n_plaq, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_cols(const double *partials, int rows, int width, int ncols, double *out,
+                           hipStream_t st)
+{
+    if (rows < 1 || ncols < 1 || ncols > width) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sum_cols, dim3(ncols), dim3(kRedThreads), 0, st, partials, rows, width, out);
     return hipGetLastError();
 }
 

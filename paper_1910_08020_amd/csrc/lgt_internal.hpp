@@ -168,6 +168,9 @@ hipError_t launch_reduce_diag(int dtype, const void *psi, int n, const uint64_t 
                               int n_masks, double *partials, hipStream_t st);
 hipError_t launch_reduce_flip(int dtype, const void *psi, int n, const uint64_t *masks_dev,
                               int n_masks, double *partials, hipStream_t st);
+// out[c] = sum of partials[row][c] over rows (device-side final sum of a reduction)
+hipError_t launch_sum_cols(const double *partials, int rows, int width, int ncols, double *out,
+                           hipStream_t st);
 hipError_t launch_reduce_dos(int dtype, const void *psi, int n, const uint32_t *ptab_dev,
                              int n_plaq, double *partials, hipStream_t st);
 // sampling: block sums -> prefix -> inverse CDF

@@ -88,6 +88,10 @@ _SIGNATURES = [
     ("lgt_tune", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lgt_plan_describe", ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_size_t]),
     ("lgt_set_plan", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("lgt_critical_point", ctypes.c_int, [_dp, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp]),
+    ("lgt_crossing", ctypes.c_int, [_dp, _dp, _dp, ctypes.c_int, _dp]),
+    ("lgt_scan", ctypes.c_int, [_VP, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t]),
     ("lgt_get_plan", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int)]),
     ("lgt_last_error", ctypes.c_char_p, [_VP]),
     ("lgt_batch_evolve", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_VP), ctypes.POINTER(lgt_schedule), ctypes.POINTER(ctypes.c_int), ctypes.c_int64, ctypes.c_int64]),
@@ -276,6 +280,41 @@ def lgt_plan_describe(ctx) -> str:
     buf = ctypes.create_string_buffer(512)
     _check(lib().lgt_plan_describe(ctx, buf, 512), ctx)
     return buf.value.decode()
+
+
+SCAN_COLUMNS = ("cx", "cz", "Z", "X", "norm")
+
+
+def lgt_critical_point(g, h, stride=1):
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    gc, d2 = ctypes.c_double(), ctypes.c_double()
+    _check(lib().lgt_critical_point(g.ctypes.data_as(_dp), h.ctypes.data_as(_dp), len(g), stride,
+                                    ctypes.byref(gc), ctypes.byref(d2)), None)
+    return gc.value, d2.value
+
+
+def lgt_crossing(g, a, b):
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    gx = ctypes.c_double()
+    _check(lib().lgt_crossing(g.ctypes.data_as(_dp), a.ctypes.data_as(_dp), b.ctypes.data_as(_dp),
+                              len(g), ctypes.byref(gx)), None)
+    return gx.value
+
+
+def lgt_scan(ctx, sched: lgt_schedule, order, first_step, substeps, n_points, masks=None) -> np.ndarray:
+    """Rows of (cx, cz, <Z>, <X>, norm, <W_0>, ...) after each block of `substeps`."""
+    keep = None
+    if masks is not None and len(masks):
+        keep = np.ascontiguousarray(masks, dtype=np.uint64)
+    nm = 0 if keep is None else len(keep)
+    out = np.zeros((int(n_points), 5 + nm), dtype=np.float64)
+    _check(lib().lgt_scan(ctx, ctypes.byref(sched), order, first_step, substeps, n_points,
+                          None if keep is None else keep.ctypes.data, nm,
+                          out.ctypes.data_as(_dp), out.size), ctx)
+    return out
 
 
 def lgt_set_plan(ctx, plan: int):

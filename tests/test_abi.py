@@ -85,3 +85,20 @@ def test_struct_layouts():
     assert ctypes.sizeof(lgt.lgt_observable) == 32
     assert lgt.lgt_info_t.state_bytes.offset == 32
     assert lgt.lgt_request.sched.offset == 24
+
+
+def test_critical_point_and_crossing_host_analysis():
+    """Host-only analysis entry points: the lowest point of d^2 h/dg^2 and a crossing."""
+    g = np.linspace(0.0, 2.0, 401)
+    g0, w = 0.986, 0.07
+    h = -w * np.log(np.cosh((g - g0) / w)) - 3.0 * g      # d2h/dg2 = -sech^2/w: valley at g0
+    gc, d2 = lgt.lgt_critical_point(g, h, stride=2)
+    assert abs(gc - g0) < 2e-3 and d2 < -1.0 / w * 0.9
+    gp = np.linspace(0.2, 3.0, 300)
+    assert abs(lgt.lgt_crossing(gp, gp, 1.0 / gp) - 1.0) < 1e-3
+    with pytest.raises(lgt.LgtError):
+        lgt.lgt_crossing(gp, gp, gp + 1.0)
+    with pytest.raises(lgt.LgtError):
+        lgt.lgt_critical_point(g[:4], h[:4], stride=2)
+    with pytest.raises(lgt.LgtError):
+        lgt.lgt_critical_point(g[::-1].copy(), h, stride=1)
