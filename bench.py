@@ -185,6 +185,39 @@ def cpu_baseline(target_s=12.0, max_steps=200):
                       f"lambda={w.lambdas[0]}, complex128 oracle, OpenMP loops, {el:.1f} s"}
 
 
+def paper_scans(lgt):
+    """The paper's own workload (Sec. 2.2, 2.6, 3.2): H = Z + g X, g from 0 to 2 in 2000 steps
+    of 0.001, each step n substeps, from the projected Z ground state, measured after every
+    step; g_c from the lowest point of d2<H>/dg2 and the <Z> = <X> crossing."""
+    out = {}
+    for name, (d, L, order, n, t_s) in {
+            "2x2x2_symmetric_n200_ts0.1": (3, (2, 2, 2), 2, 200, 0.1),
+            "3x3_first_order_n500_ts0.02": (2, (3, 3), 1, 500, 0.02)}.items():
+        ctx = lgt.lgt_create(d, list(L), 1, lgt.LGT_C64)
+        try:
+            lgt.lgt_reset(ctx, lgt.LGT_INIT_ZGROUND, 0)
+            s = lgt.make_schedule(t_s * 2000, n * 2000, ramp=lgt.LGT_RAMP_COUPLING, g0=0.0, g1=2.0)
+            t0 = time.perf_counter()
+            rows = lgt.lgt_scan(ctx, s, order, 0, n, 2000)
+            el = time.perf_counter() - t0
+        finally:
+            lgt.lgt_destroy(ctx)
+        g, z, x = rows[:, 0], rows[:, 2], rows[:, 3]
+        r = {"substeps": n * 2000, "measurements": 2000, "seconds": el,
+             "us_per_substep_incl_measurement": el / (n * 2000) * 1e6,
+             "g_c_d2H_min": lgt.lgt_critical_point(g, z + g * x, stride=10)[0],
+             "Z_at_g0.001": float(z[0]), "X_at_g2": float(x[-1]),
+             "max_norm_drift": float(np.max(np.abs(rows[:, 4] - 1)))}
+        try:
+            r["Z_X_crossing"] = lgt.lgt_crossing(g, z, x)
+        except lgt.LgtError:
+            r["Z_X_crossing"] = None
+        r["Z(g)-X(1/g) at g=0.5,0.8"] = [float(z[499] - x[1999]), float(z[799] - x[1249])]
+        out[name] = r
+    out["paper_values"] = {"g_c_2x2x2": 0.986, "g_c_3x3": 0.380, "crossing_2x2x2": 1.0}
+    return out
+
+
 def variants(lgt):
     """Per-Trotter-step time of the other precisions, forms and sizes (secondary)."""
     out = {}
@@ -359,6 +392,7 @@ def main():
         line["lambda_scan"] = lambda_scan(lgt)
         line["serving"] = serving(lgt, args.serve_requests, args.serve_rate)
         line["variants"] = variants(lgt)
+        line["paper_scans"] = paper_scans(lgt)
         line["precision"] = precision(lgt)
     print(json.dumps(line), flush=True)
 

@@ -191,8 +191,13 @@ typedef enum {
     LGT_OBS_SIGMAX = 5,  /* out[l] = <sigma^x_l>, l < n_links                           */
     LGT_OBS_SIGMAZ = 6,  /* out[l] = <sigma^z_l>                                        */
     LGT_OBS_ENERGY = 7,  /* out[0] = -cx sum_l <sigma^x_l> - cz sum_p <U_p>             */
-    LGT_OBS_ZDOS = 8     /* out[m] = weight of basis states with m odd plaquettes,
+    LGT_OBS_ZDOS = 8,    /* out[m] = weight of basis states with m odd plaquettes,
                             i.e. Z = -sum U_p = 2m - n_plaq (Sec. 3.3), m <= n_plaq     */
+    LGT_OBS_XDOS = 9     /* out[k] = weight of sigma^x eigenstates with k links at
+                            sigma^x = -1, i.e. X = -sum sigma^x = 2k - n_links (Sec. 3.3),
+                            k <= n_links: the Walsh-Hadamard transform of a device copy
+                            of the state (the state itself is left unchanged), then a
+                            popcount histogram; needs one extra state-sized buffer      */
 } lgt_obs_kind;
 
 typedef struct {

@@ -282,6 +282,26 @@ def zdos(psi, lat: Lattice) -> np.ndarray:
     return out / norm2(psi, lat.N)
 
 
+def xdos(psi: np.ndarray, N: int) -> np.ndarray:
+    """D(x) of Sec. 3.3: weights |<c_x|psi>|^2 of the sigma^x eigenstates |c_x> (link l at
+    sigma^x = +1 for c_l = 0, -1 for c_l = 1), binned by k = popcount(c), X = 2k - N.
+    <c_x|b> = 2^(-N/2) (-1)^(b.c): a Hadamard on every link, written out per link."""
+    phi = np.array(psi, dtype=np.complex128)
+    r = 1.0 / np.sqrt(2.0)
+    for q in range(N):
+        v = phi.reshape(-1, 2, 1 << q)
+        a0 = v[:, 0, :].copy()
+        a1 = v[:, 1, :].copy()
+        v[:, 0, :] = (a0 + a1) * r
+        v[:, 1, :] = (a0 - a1) * r
+    c = np.arange(1 << N, dtype=np.uint64)
+    pop = np.zeros(1 << N, dtype=np.int64)
+    for q in range(N):
+        pop += ((c >> np.uint64(q)) & np.uint64(1)).astype(np.int64)
+    w = np.abs(phi) ** 2
+    return np.bincount(pop, weights=w, minlength=N + 1) / w.sum()
+
+
 def readout(psi: np.ndarray, lat: Lattice, cx_final: float, cz_final: float) -> dict:
     """The full readout: norm, <U_p>, <sigma^z_l>, <sigma^x_l>, <G_i>, energy.
 

@@ -748,6 +748,7 @@ lgt_status lgt_measure(lgt_ctx *c, const lgt_observable *obs, double *out, size_
         break;
     case LGT_OBS_ENERGY: need = 1; break;
     case LGT_OBS_ZDOS: need = lat.n_plaq + 1; break;
+    case LGT_OBS_XDOS: need = lat.n_links + 1; break;
     default: return fail(c, LGT_E_INVALID, "unknown observable");
     }
     if (out_len < need) return fail(c, LGT_E_INVALID, "output array too short");
@@ -770,6 +771,32 @@ lgt_status lgt_measure(lgt_ctx *c, const lgt_observable *obs, double *out, size_
             long double acc = 0;
             for (int b = 0; b < g; ++b) acc += c->partials_host[(size_t)b * kPartialWidth + m];
             out[m] = (double)(acc / nrm);
+        }
+        return LGT_OK;
+    }
+    if (obs->kind == LGT_OBS_XDOS) {
+        // sigma^x basis: Hadamard on every link of a copy, then the popcount histogram
+        if (lat.n_links > kMaxPlaq) return fail(c, LGT_E_UNSUPPORTED, "X-DOS supports <= 32 links");
+        void *tmp = nullptr;
+        if (hipMalloc(&tmp, c->state_bytes) != hipSuccess) return fail(c, LGT_E_OOM, "X-DOS buffer");
+        hipError_t e = hipMemcpyAsync(tmp, c->state, c->state_bytes, hipMemcpyDeviceToDevice, c->stream);
+        for (int q = 0; q < lat.n_links && e == hipSuccess; ++q)
+            e = timed(c, KF_GATE_H, [&] { return launch_gate_h(c->dtype, tmp, lat.n_links, q, c->stream); });
+        if (e == hipSuccess)
+            e = timed(c, KF_RED_DOS, [&] {
+                return launch_reduce_popcount(c->dtype, tmp, lat.n_links, c->ptab_dev, c->partials, c->stream);
+            });
+        const int g = reduce_blocks(lat.n_links);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->partials_host.data(), c->partials, sizeof(double) * g * kPartialWidth,
+                               hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return fail(c, LGT_E_DEVICE, std::string("X-DOS: ") + hipGetErrorString(e));
+        for (int k = 0; k <= lat.n_links; ++k) {
+            long double acc = 0;
+            for (int b = 0; b < g; ++b) acc += c->partials_host[(size_t)b * kPartialWidth + k];
+            out[k] = (double)(acc / nrm);
         }
         return LGT_OK;
     }

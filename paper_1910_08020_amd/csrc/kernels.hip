@@ -859,6 +859,26 @@ __global__ void k_init(cplx_t<T> *psi, int n, int init, uint64_t basis, T amp,
 // circuit-form gates, one full-state pass each (eq. (ara) and the R_x layer)
 // ---------------------------------------------------------------------------
 template <typename T>
+__global__ void k_gate_h(cplx_t<T> *psi, int n, int q)
+{
+    // Hadamard on link q: (a0, a1) <- ((a0 + a1) / sqrt 2, (a0 - a1) / sqrt 2)
+    const T r = T(0.70710678118654752440);
+    const uint64_t half = 1ull << (n - 1), lo = (1ull << q) - 1;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < half;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i0 = ((p & ~lo) << 1) | (p & lo), i1 = i0 | (lo + 1);
+        const cplx_t<T> a0 = psi[i0], a1 = psi[i1];
+        cplx_t<T> b0, b1;
+        b0.x = (a0.x + a1.x) * r;
+        b0.y = (a0.y + a1.y) * r;
+        b1.x = (a0.x - a1.x) * r;
+        b1.y = (a0.y - a1.y) * r;
+        psi[i0] = b0;
+        psi[i1] = b1;
+    }
+}
+
+template <typename T>
 __global__ void k_gate_rx(cplx_t<T> *psi, int n, int q, T c, T s)
 {
     // R_x(phi) = exp(-i sigma^x phi/2): (a0, a1) <- (c a0 - i s a1, -i s a0 + c a1)
@@ -1003,7 +1023,9 @@ __global__ __launch_bounds__(kRedThreads) void k_sum_cols(const double *__restri
 }
 
 // Z density of states: acc[m] += |psi_b|^2 for the m = popcount(P(b)) bin
-template <typename T>
+// BYPOP: the bin is popcount(b) itself (a density of states in the basis of a transformed
+// copy of the state), otherwise the number of odd plaquettes of b
+template <typename T, bool BYPOP>
 __global__ __launch_bounds__(kRedThreads) void k_red_dos(const cplx_t<T> *__restrict__ psi, int n,
                                                          const uint32_t *__restrict__ ptab_g,
                                                          int n_plaq, double *partials)
@@ -1019,7 +1041,7 @@ __global__ __launch_bounds__(kRedThreads) void k_red_dos(const cplx_t<T> *__rest
          b += (uint64_t)gridDim.x * kRedThreads) {
         const cplx_t<T> a = psi[b];
         const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
-        const int m = __popc(syndrome(b, ptab));
+        const int m = BYPOP ? __popcll(b) : __popc(syndrome(b, ptab));
 #pragma unroll
         for (int k = 0; k <= kMaxPlaq; ++k) acc[k] += (m == k) ? p : 0.0;
     }
@@ -1105,7 +1127,7 @@ const char *kernel_family_name(int kf)
     static const char *names[KF_COUNT] = {"init", "pass_low", "pass_high", "phase", "small",
                                           "gate_rx", "gate_rz", "gate_cnot", "reduce_diag",
                                           "reduce_flip", "reduce_dos", "sample", "tile_low",
-                                          "tile_high"};
+                                          "tile_high", "gate_h"};
     return (kf >= 0 && kf < KF_COUNT) ? names[kf] : "?";
 }
 
@@ -1389,11 +1411,36 @@ hipError_t launch_reduce_dos(int dtype, const void *psi, int n, const uint32_t *
 {
     const int g = reduce_blocks(n);
     if (dtype == LGT_C64)
-        hipLaunchKernelGGL(k_red_dos<float>, dim3(g), dim3(kRedThreads), 0, st,
+        hipLaunchKernelGGL((k_red_dos<float, false>), dim3(g), dim3(kRedThreads), 0, st,
                            (const float2 *)psi, n, ptab_dev, n_plaq, partials);
     else
-        hipLaunchKernelGGL(k_red_dos<double>, dim3(g), dim3(kRedThreads), 0, st,
+        hipLaunchKernelGGL((k_red_dos<double, false>), dim3(g), dim3(kRedThreads), 0, st,
                            (const double2 *)psi, n, ptab_dev, n_plaq, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_popcount(int dtype, const void *psi, int n, const uint32_t *ptab_dev,
+                                  double *partials, hipStream_t st)
+{
+    if (n > kMaxPlaq) return hipErrorInvalidValue;   // bins 0..n must fit the partial width
+    const int g = reduce_blocks(n);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL((k_red_dos<float, true>), dim3(g), dim3(kRedThreads), 0, st,
+                           (const float2 *)psi, n, ptab_dev, 0, partials);
+    else
+        hipLaunchKernelGGL((k_red_dos<double, true>), dim3(g), dim3(kRedThreads), 0, st,
+                           (const double2 *)psi, n, ptab_dev, 0, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate_h(int dtype, void *psi, int n, int q, hipStream_t st)
+{
+    const uint64_t half = 1ull << (n - 1);
+    const unsigned g = grid_for(half, 256, 16384);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_gate_h<float>, dim3(g), dim3(256), 0, st, (float2 *)psi, n, q);
+    else
+        hipLaunchKernelGGL(k_gate_h<double>, dim3(g), dim3(256), 0, st, (double2 *)psi, n, q);
     return hipGetLastError();
 }
 

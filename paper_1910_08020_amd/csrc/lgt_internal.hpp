@@ -121,7 +121,7 @@ std::string describe_plan(const PassPlan &p, int n_links);
 // ---------------------------------------------------------------------------
 enum KernelFamily {
     KF_INIT = 0, KF_LOW, KF_HIGH, KF_PHASE, KF_SMALL, KF_GATE_RX, KF_GATE_RZ, KF_GATE_CNOT,
-    KF_RED_DIAG, KF_RED_FLIP, KF_RED_DOS, KF_SAMPLE, KF_TILE_LOW, KF_TILE_HIGH, KF_COUNT
+    KF_RED_DIAG, KF_RED_FLIP, KF_RED_DOS, KF_SAMPLE, KF_TILE_LOW, KF_TILE_HIGH, KF_GATE_H, KF_COUNT
 };
 const char *kernel_family_name(int kf);
 
@@ -171,6 +171,10 @@ hipError_t launch_reduce_flip(int dtype, const void *psi, int n, const uint64_t 
 // out[c] = sum of partials[row][c] over rows (device-side final sum of a reduction)
 hipError_t launch_sum_cols(const double *partials, int rows, int width, int ncols, double *out,
                            hipStream_t st);
+// histogram of |psi_b|^2 over popcount(b), bins 0..n (n <= kMaxPlaq)
+hipError_t launch_reduce_popcount(int dtype, const void *psi, int n, const uint32_t *ptab_dev,
+                                  double *partials, hipStream_t st);
+hipError_t launch_gate_h(int dtype, void *psi, int n, int q, hipStream_t st);
 hipError_t launch_reduce_dos(int dtype, const void *psi, int n, const uint32_t *ptab_dev,
                              int n_plaq, double *partials, hipStream_t st);
 // sampling: block sums -> prefix -> inverse CDF

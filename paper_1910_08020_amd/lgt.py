@@ -22,7 +22,7 @@ LGT_INIT_PLUS, LGT_INIT_ZGROUND, LGT_INIT_BASIS = 0, 1, 2
 LGT_RAMP_PLAQ, LGT_RAMP_COUPLING, LGT_RAMP_EXPLICIT = 0, 1, 2
 LGT_PLAN_NO_MERGE = 8
 (LGT_OBS_NORM, LGT_OBS_Z, LGT_OBS_X, LGT_OBS_PLAQ, LGT_OBS_STAR, LGT_OBS_SIGMAX, LGT_OBS_SIGMAZ,
- LGT_OBS_ENERGY, LGT_OBS_ZDOS) = range(9)
+ LGT_OBS_ENERGY, LGT_OBS_ZDOS, LGT_OBS_XDOS) = range(10)
 
 STATUS_NAMES = {0: "LGT_OK", 1: "LGT_E_INVALID", 2: "LGT_E_UNSUPPORTED", 3: "LGT_E_OOM",
                 4: "LGT_E_DEVICE", 5: "LGT_E_STATE", 6: "LGT_E_BUSY"}

@@ -67,3 +67,49 @@ def test_scan_validation():
             assert ex.value.status == lgt.LGT_E_INVALID
         with pytest.raises(lgt.LgtError):
             lgt.lgt_scan(ctx, s, SYM, 0, 2, 5, [1 << 9])
+
+
+def _paper_scan(d, L, order, n, t_s, N_s=2000, g_f=2.0):
+    """Sec. 2.6 parameters: g from 0 to 2 in N_s = 2000 steps of g_s = 0.001, each step n
+    substeps of t_s / n, from the projected Z ground state, complex64."""
+    with gpu_ctx(d, L, C64) as ctx:
+        lgt.lgt_reset(ctx, lgt.LGT_INIT_ZGROUND, 0)
+        s = lgt.make_schedule(t_s * N_s, n * N_s, ramp=lgt.LGT_RAMP_COUPLING, g0=0.0, g1=g_f)
+        return lgt.lgt_scan(ctx, s, order, 0, n, N_s)
+
+
+def test_paper_scan_3x3_first_order():
+    """3x3, first order, n = 500, t_s = 0.02 (Sec. 2.6): the energy stays within the
+    adiabatic error of the exact ground energy of the sector (dual Ising, exact
+    diagonalisation), never below it, and d2<H>/dg2 bottoms out near the printed
+    g_c = 0.380 (Sec. 3.2)."""
+    from oracle.dual import DualIsing
+    rows = _paper_scan(2, (3, 3), TROT, 500, 0.02)
+    g, z, x = rows[:, 0], rows[:, 2], rows[:, 3]
+    assert abs(z[0] + 9) < 1e-4
+    lat = oracle.Lattice(2, (3, 3))
+    du = DualIsing(lat.plaq, lat.N)
+    w, V = np.linalg.eigh(du.even_projector())
+    B = V[:, w > 0.5]
+    for k in range(0, 2000, 50):
+        e0 = np.linalg.eigvalsh(B.conj().T @ du.hamiltonian(g[k], 1.0) @ B)[0]
+        dev = z[k] + g[k] * x[k] - e0
+        assert -1e-3 < dev < 0.05, (g[k], dev)
+    gc, _ = lgt.lgt_critical_point(g, z + g * x, stride=10)
+    assert 0.36 < gc < 0.41
+
+
+def test_paper_scan_2x2x2_symmetric():
+    """2x2x2, symmetric, n = 200, t_s = 0.1 (Sec. 2.6): <Z> and <X> cross at the self-dual
+    point g = 1, <Z>(g) = <X>(1/g) (eq. (dual)), and d2<H>/dg2 bottoms out near the
+    printed g_c = 0.986 (Sec. 3.2)."""
+    rows = _paper_scan(3, (2, 2, 2), SYM, 200, 0.1)
+    g, z, x = rows[:, 0], rows[:, 2], rows[:, 3]
+    assert abs(z[0] + 24) < 1e-4
+    assert np.max(np.abs(rows[:, 4] - 1)) < 5e-3
+    assert 0.99 < lgt.lgt_crossing(g, z, x) < 1.01
+    gc, _ = lgt.lgt_critical_point(g, z + g * x, stride=10)
+    assert 0.96 < gc < 1.01
+    for gq in (0.5, 0.6, 0.7, 0.8, 0.9):
+        i, j = int(round(gq * 1000)) - 1, int(round(1000 / gq)) - 1
+        assert abs(z[i] - x[j]) < 0.02, gq
