@@ -214,6 +214,31 @@ def paper_scans(lgt):
             r["Z_X_crossing"] = None
         r["Z(g)-X(1/g) at g=0.5,0.8"] = [float(z[499] - x[1999]), float(z[799] - x[1249])]
         out[name] = r
+    # Sec. 3.5: the four topological sectors of 3x3, splittings E_i1^(1/4) linear in g
+    E = {}
+    t0 = time.perf_counter()
+    for signs in [(1, 1), (-1, 1), (1, -1), (-1, -1)]:
+        ctx = lgt.lgt_create(2, [3, 3], 1, lgt.LGT_C64)
+        try:
+            lgt.lgt_reset(ctx, lgt.LGT_INIT_ZGROUND, 0)
+            for mu, sgn in enumerate(signs):
+                if sgn < 0:
+                    lgt.lgt_apply_pauli(ctx, 0, lgt.lgt_line_mask(ctx, 0, mu))
+            s = lgt.make_schedule(0.02 * 500, 500 * 500, ramp=lgt.LGT_RAMP_COUPLING, g0=0.0, g1=0.5)
+            rows = lgt.lgt_scan(ctx, s, 1, 0, 500, 500)
+        finally:
+            lgt.lgt_destroy(ctx)
+        E[signs] = rows[:, 2] + rows[:, 0] * rows[:, 3]
+        g = rows[:, 0]
+    sl = slice(49, 300)
+    fits = {}
+    for name, key in (("E21", (-1, 1)), ("E31", (1, -1)), ("E41", (-1, -1))):
+        a, b = np.polyfit(g[sl], np.abs(E[key] - E[(1, 1)])[sl] ** 0.25, 1)
+        fits[name] = {"slope": float(a), "intercept": float(b)}
+    out["3x3_sectors_first_order_to_g0.5"] = {
+        "seconds": time.perf_counter() - t0, "fit_window_g": [0.05, 0.30],
+        "fits_E_i1^(1/4)=a*g+b": fits,
+        "paper": {"E21": [1.88719, 0.02516], "E41": [2.08307, 0.0441229]}}
     out["paper_values"] = {"g_c_2x2x2": 0.986, "g_c_3x3": 0.380, "crossing_2x2x2": 1.0}
     return out
 

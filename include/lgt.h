@@ -130,6 +130,14 @@ lgt_status lgt_wilson_mask(const lgt_ctx *ctx, int site, int mu, int nu, int a, 
 
 /* lgt_line_mask: non-contractible loop C_mu through `site` (Sec. 2.1). */
 lgt_status lgt_line_mask(const lgt_ctx *ctx, int site, int mu, uint64_t *mask);
+/*
+ * lgt_thooft_mask: links of the 't Hooft operator V_mu = prod sigma^x (Sec. 2.1, the
+ * definition after Fig. fig_torus_lattice): the mu-links of the sites on the plane
+ * x_mu = 0, i.e. every link piercing the closed dual surface between x_mu = 0 and 1.
+ * With this labelling the Wilson line of lgt_line_mask(.., mu) shares exactly one link with
+ * V_mu and anticommutes with it, and commutes with V_nu for nu != mu.  Host only.
+ */
+lgt_status lgt_thooft_mask(const lgt_ctx *ctx, int mu, uint64_t *mask);
 
 /* lgt_reset: overwrite the state (Sec. 2.3). basis_index < 2^N for LGT_INIT_BASIS. */
 lgt_status lgt_reset(lgt_ctx *ctx, lgt_init init, uint64_t basis_index);
@@ -214,6 +222,15 @@ typedef struct {
  * LGT_E_INVALID and writes nothing.
  */
 lgt_status lgt_measure(lgt_ctx *ctx, const lgt_observable *obs, double *out, size_t out_len);
+
+/*
+ * lgt_apply_pauli: psi <- X^xmask Z^zmask psi, a product of sigma^z over the zmask links
+ * followed by sigma^x over the xmask links (Sec. 3.5: Wegner-Wilson operators W_mu on
+ * non-contractible loops move the initial state between topological sectors; 't Hooft
+ * operators V_mu are the sigma^x strings).  In place on the device, stream-ordered.
+ * E_INVALID for masks with bits at or beyond N_l.
+ */
+lgt_status lgt_apply_pauli(lgt_ctx *ctx, uint64_t xmask, uint64_t zmask);
 
 /*
  * lgt_scan: the stepwise adiabatic evolution of Sec. 2.2, paused for measurement after every

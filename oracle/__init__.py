@@ -150,6 +150,19 @@ class Lattice:
         """Non-contractible loop C_mu: L_mu links straight along mu (Sec. 2.1)."""
         return self.walk(start_site, [mu + 1] * self.L[mu])
 
+    def thooft(self, mu: int) -> list:
+        """Links of the 't Hooft operator V_mu (sigma^x string, Sec. 2.1): the mu-links of
+        the sites with coordinate x_mu = 0, which pierce one closed dual surface."""
+        out = []
+        for s in range(self.n_sites):
+            x, t = [], s
+            for nu in range(self.d):
+                x.append(t % self.L[nu])
+                t //= self.L[nu]
+            if x[mu] == 0:
+                out.append(self.d * s + (self.d - 1 - mu))
+        return out
+
     def site(self, x) -> int:
         s, stride = 0, 1
         for mu in range(self.d):

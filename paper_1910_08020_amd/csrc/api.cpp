@@ -542,6 +542,24 @@ lgt_status lgt_line_mask(const lgt_ctx *c, int site, int mu, uint64_t *mask)
     return LGT_OK;
 }
 
+lgt_status lgt_thooft_mask(const lgt_ctx *c, int mu, uint64_t *mask)
+{
+    if (!c || !mask) return fail(nullptr, LGT_E_INVALID, "null argument");
+    if (mu < 0 || mu >= c->lat.d) return fail(const_cast<lgt_ctx *>(c), LGT_E_INVALID, "bad direction");
+    *mask = thooft_mask(c->lat, mu);
+    return LGT_OK;
+}
+
+lgt_status lgt_apply_pauli(lgt_ctx *c, uint64_t xmask, uint64_t zmask)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    const int n = c->lat.n_links;
+    if ((xmask >> n) || (zmask >> n)) return fail(c, LGT_E_INVALID, "mask has bits beyond N");
+    HIPCHK(c, launch_pauli(c->dtype, c->state, n, xmask, zmask, c->stream));
+    return LGT_OK;
+}
+
 lgt_status lgt_reset(lgt_ctx *c, lgt_init init, uint64_t basis_index)
 {
     lgt_status s = check_ctx(c);

@@ -878,6 +878,40 @@ __global__ void k_gate_h(cplx_t<T> *psi, int n, int q)
     }
 }
 
+// (X^x Z^z psi)_b = (-1)^popcount((b ^ x) & z) psi_{b ^ x}; pairs (b, b ^ x) are handled by
+// the thread whose b has a zero at the lowest bit of x (x != 0), single amplitudes otherwise
+template <typename T>
+__global__ void k_pauli(cplx_t<T> *psi, int n, uint64_t x, uint64_t z)
+{
+    using C = cplx_t<T>;
+    auto sgn = [&](uint64_t b) -> T { return (__popcll(b & z) & 1) ? T(-1) : T(1); };
+    if (x == 0) {
+        for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < (1ull << n);
+             b += (uint64_t)gridDim.x * blockDim.x) {
+            C a = psi[b];
+            const T s = sgn(b);
+            a.x *= s;
+            a.y *= s;
+            psi[b] = a;
+        }
+        return;
+    }
+    const uint64_t lo = (x & (~x + 1)) - 1;   // bits below the lowest set bit of x
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < (1ull << (n - 1));
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = ((p & ~lo) << 1) | (p & lo), c = b ^ x;
+        C a0 = psi[b], a1 = psi[c];
+        const T s0 = sgn(c), s1 = sgn(b);
+        C r0, r1;
+        r0.x = s0 * a1.x;
+        r0.y = s0 * a1.y;
+        r1.x = s1 * a0.x;
+        r1.y = s1 * a0.y;
+        psi[b] = r0;
+        psi[c] = r1;
+    }
+}
+
 template <typename T>
 __global__ void k_gate_rx(cplx_t<T> *psi, int n, int q, T c, T s)
 {
@@ -1430,6 +1464,17 @@ hipError_t launch_reduce_popcount(int dtype, const void *psi, int n, const uint3
     else
         hipLaunchKernelGGL((k_red_dos<double, true>), dim3(g), dim3(kRedThreads), 0, st,
                            (const double2 *)psi, n, ptab_dev, 0, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_pauli(int dtype, void *psi, int n, uint64_t xmask, uint64_t zmask, hipStream_t st)
+{
+    if (n < 1 || (xmask >> n) || (zmask >> n)) return hipErrorInvalidValue;
+    const unsigned g = grid_for(1ull << n, 256, 16384);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_pauli<float>, dim3(g), dim3(256), 0, st, (float2 *)psi, n, xmask, zmask);
+    else
+        hipLaunchKernelGGL(k_pauli<double>, dim3(g), dim3(256), 0, st, (double2 *)psi, n, xmask, zmask);
     return hipGetLastError();
 }
 

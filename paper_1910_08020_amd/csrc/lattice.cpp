@@ -107,6 +107,18 @@ uint64_t line_mask(const Lattice &lat, int site, int mu)
     return m;
 }
 
+uint64_t thooft_mask(const Lattice &lat, int mu)
+{
+    // the mu-links of the sites on the plane x_mu = 0: every link that pierces the closed
+    // dual surface between the planes x_mu = 0 and x_mu = 1
+    int stride = 1;
+    for (int nu = 0; nu < mu; ++nu) stride *= lat.L[nu];
+    uint64_t m = 0;
+    for (int s = 0; s < lat.n_sites; ++s)
+        if ((s / stride) % lat.L[mu] == 0) m |= 1ull << lat.link(s, mu);
+    return m;
+}
+
 void build_parity_tables(const Lattice &lat, uint32_t tab[kParityBytes][256])
 {
     for (int k = 0; k < kParityBytes; ++k)

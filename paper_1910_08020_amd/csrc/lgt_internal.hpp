@@ -33,6 +33,7 @@ struct Lattice {
 std::string build_lattice(int d, const int *L, Lattice &out);
 uint64_t region_mask(const Lattice &lat, int site, int mu, int nu, int a, int b);
 uint64_t line_mask(const Lattice &lat, int site, int mu);
+uint64_t thooft_mask(const Lattice &lat, int mu);
 
 // Plaquette syndrome tables: P(b) = XOR_k tab[k][(b >> 8k) & 255], bit p of P(b)
 // is the parity of plaquette p on basis state b.  P is linear over GF(2).
@@ -175,6 +176,8 @@ hipError_t launch_sum_cols(const double *partials, int rows, int width, int ncol
 hipError_t launch_reduce_popcount(int dtype, const void *psi, int n, const uint32_t *ptab_dev,
                                   double *partials, hipStream_t st);
 hipError_t launch_gate_h(int dtype, void *psi, int n, int q, hipStream_t st);
+// psi <- X^xmask Z^zmask psi (Pauli string: Z on the zmask links, then X on the xmask links)
+hipError_t launch_pauli(int dtype, void *psi, int n, uint64_t xmask, uint64_t zmask, hipStream_t st);
 hipError_t launch_reduce_dos(int dtype, const void *psi, int n, const uint32_t *ptab_dev,
                              int n_plaq, double *partials, hipStream_t st);
 // sampling: block sums -> prefix -> inverse CDF

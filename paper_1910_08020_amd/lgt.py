@@ -88,6 +88,8 @@ _SIGNATURES = [
     ("lgt_tune", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lgt_plan_describe", ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_size_t]),
     ("lgt_set_plan", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("lgt_thooft_mask", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
+    ("lgt_apply_pauli", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_uint64]),
     ("lgt_critical_point", ctypes.c_int, [_dp, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp]),
     ("lgt_crossing", ctypes.c_int, [_dp, _dp, _dp, ctypes.c_int, _dp]),
     ("lgt_scan", ctypes.c_int, [_VP, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
@@ -315,6 +317,16 @@ def lgt_scan(ctx, sched: lgt_schedule, order, first_step, substeps, n_points, ma
                           None if keep is None else keep.ctypes.data, nm,
                           out.ctypes.data_as(_dp), out.size), ctx)
     return out
+
+
+def lgt_thooft_mask(ctx, mu) -> int:
+    m = ctypes.c_uint64()
+    _check(lib().lgt_thooft_mask(ctx, mu, ctypes.byref(m)), ctx)
+    return m.value
+
+
+def lgt_apply_pauli(ctx, xmask=0, zmask=0):
+    _check(lib().lgt_apply_pauli(ctx, xmask, zmask), ctx)
 
 
 def lgt_set_plan(ctx, plan: int):
