@@ -55,7 +55,8 @@ typedef enum { LGT_C64 = 0, LGT_C128 = 1 } lgt_dtype;
 typedef enum { LGT_ORDER_TROTTER = 1, LGT_ORDER_SYMMETRIC = 2 } lgt_order;
 
 /* FUSED: link layer in LDS-tiled passes with the plaquette phases folded into
- * the last pass.  CIRCUIT: one full-state pass per gate, as in eq. (ara)
+ * the pass that ends a step (consecutive steps share that pass, see lgt_set_plan).
+ * CIRCUIT: one full-state pass per gate, as in eq. (ara)
  * (CNOT ladder onto the last plaquette link, R_z, inverse ladder) and the
  * R_x link layer of Sec. 2.2. */
 typedef enum { LGT_FORM_FUSED = 0, LGT_FORM_CIRCUIT = 1 } lgt_form;
@@ -343,8 +344,8 @@ const char *lgt_last_error(const lgt_ctx *ctx);
 /*
  * lgt_batch_evolve: advance n contexts that share d, L and dtype by the same
  * step range of their own schedules (each may have its own couplings, e.g. a
- * lambda scan).  Equivalent to calling lgt_evolve on each context, but every
- * pass is one launch over all instances, and small lattices (N <= 12) run
+ * lambda scan).  Equivalent to calling lgt_evolve on each context (bit for bit),
+ * but every pass is one launch over all instances, and small lattices (N <= 12) run
  * every step of the range in a single launch with the state held on chip.
  * Work is enqueued on ctxs[0]'s stream; the other contexts' streams are
  * synchronised first.  Errors as lgt_evolve; LGT_E_INVALID if the contexts do
