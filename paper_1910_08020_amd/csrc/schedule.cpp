@@ -109,14 +109,16 @@ static void round_pair_norm(double x, double y, double target2, float &fx, float
     cx[3] = std::nextafter(x0, INFINITY);  cx[4] = std::nextafter(cx[3], INFINITY);
     cy[1] = std::nextafter(y0, -INFINITY); cy[0] = std::nextafter(cy[1], -INFINITY);
     cy[3] = std::nextafter(y0, INFINITY);  cy[4] = std::nextafter(cy[3], INFINITY);
-    long double best = std::numeric_limits<long double>::infinity(), bestd = best;
+    // a float squared is exact in double (24-bit significands), so a*a + b*b carries one
+    // rounding at most: far below the spacing of the candidates' magnitudes (~1e-7)
+    double best = std::numeric_limits<double>::infinity(), bestd = best;
     fx = x0;
     fy = y0;
     for (int i = 0; i < 5; ++i)
         for (int k = 0; k < 5; ++k) {
-            long double a = cx[i], b = cy[k];
-            long double e = std::fabs(a * a + b * b - (long double)target2);
-            long double dd = (a - x) * (a - x) + (b - y) * (b - y);
+            const double a = cx[i], b = cy[k];
+            const double e = std::fabs(a * a + b * b - target2);
+            const double dd = (a - x) * (a - x) + (b - y) * (b - y);
             if (e < best || (e == best && dd < bestd)) {
                 best = e;
                 bestd = dd;
