@@ -118,7 +118,8 @@ hipError_t ensure_stage(lgt_ctx *c, size_t need)
 }
 
 // --- profiling: HIP events around launches on the context stream ----------
-hipError_t prof_begin(lgt_ctx *c, int kf, ProfEvent &pe)
+// two events from the context's pool for one timed launch
+hipError_t prof_take(lgt_ctx *c, int kf, ProfEvent &pe)
 {
     pe.kf = kf;
     if (c->pool.size() < 2) {
@@ -131,7 +132,7 @@ hipError_t prof_begin(lgt_ctx *c, int kf, ProfEvent &pe)
     }
     pe.a = c->pool.back(); c->pool.pop_back();
     pe.b = c->pool.back(); c->pool.pop_back();
-    return hipEventRecord(pe.a, c->stream);
+    return hipSuccess;
 }
 
 hipError_t prof_harvest(lgt_ctx *c)
@@ -157,12 +158,29 @@ hipError_t timed(lgt_ctx *c, int kf, F &&launch)
     if (!c->profiling) return launch();
     if (c->prof_seen[kf]++ % c->prof_stride) return launch();
     ProfEvent pe;
-    hipError_t e = prof_begin(c, kf, pe);
-    if (e != hipSuccess) return e;
-    e = launch();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(pe.b, c->stream);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (kf == KF_TILE_LOW || kf == KF_TILE_HIGH) {
+        // the tile launchers time their kernels themselves, on the dispatch
+        e = prof_take(c, kf, pe);
+        if (e != hipSuccess) return e;
+        LaunchTiming lt{pe.a, pe.b, false};
+        g_launch_timing = &lt;
+        e = launch();
+        g_launch_timing = nullptr;
+        if (e != hipSuccess || !lt.used) {
+            c->pool.push_back(pe.a);
+            c->pool.push_back(pe.b);
+            return e;
+        }
+    } else {
+        e = prof_take(c, kf, pe);
+        if (e == hipSuccess) e = hipEventRecord(pe.a, c->stream);
+        if (e != hipSuccess) return e;
+        e = launch();
+        if (e != hipSuccess) return e;
+        e = hipEventRecord(pe.b, c->stream);
+        if (e != hipSuccess) return e;
+    }
     c->pending.push_back(pe);
     if (c->pending.size() >= 4096) return prof_harvest(c);
     return hipSuccess;
@@ -306,12 +324,25 @@ hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_
                                int count, int pre_first, int post_off, const uint8_t *forms,
                                int plan_sel, hipStream_t st, void *prof_ctx)
 {
+    FusedCursor cur;
+    return enqueue_fused_range(dtype, n, n_plaq, dev_inst, n_inst, count, 0, count, pre_first,
+                               post_off, forms, plan_sel, st, prof_ctx, cur);
+}
+
+hipError_t enqueue_fused_range(int dtype, int n, int n_plaq, const DevInst *dev_inst, int n_inst,
+                               int count, int j_begin, int j_end, int pre_first, int post_off,
+                               const uint8_t *forms, int plan_sel, hipStream_t st,
+                               void *prof_ctx, FusedCursor &cur)
+{
     lgt_ctx *pc = (lgt_ctx *)prof_ctx;
     auto run = [&](int kf, auto &&launch) -> hipError_t {
         if (pc && pc->profiling) return timed(pc, kf, launch);
         return launch();
     };
+    if (j_begin < 0 || j_end > count || j_begin > j_end) return hipErrorInvalidValue;
     if (small_supported(dtype, n)) {
+        // one kernel runs every step: no partial ranges
+        if (j_begin != 0 || j_end != count) return hipErrorInvalidValue;
         // the small kernel reads phase[ph0] first when pre_first >= 0
         return run(KF_SMALL, [&] {
             return launch_small(dtype, dev_inst, n_inst, n, count, pre_first >= 0 ? 1 : 0, n_plaq, st);
@@ -321,8 +352,8 @@ hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_
     const int np = plan.n_passes;
     // merged plans walk the passes forwards and backwards in turn, so a step's last pass
     // is the next step's first: one launch applies both rotations around the phase
-    bool fwd = true, merged_in = false;
-    for (int j = 0; j < count; ++j) {
+    bool fwd = cur.fwd, merged_in = cur.merged_in;
+    for (int j = j_begin; j < j_end; ++j) {
         auto form_at = [&](int i) { return forms ? ((forms[i] & 3) ? (forms[i] & 3) : 1) : 3; };
         const bool merge_out = plan.merge && j + 1 < count;
         const int fm = form_at(j) | (merge_out ? form_at(j + 1) << 2 : 0);
@@ -362,6 +393,8 @@ hipError_t enqueue_fused_steps(int dtype, int n, int n_plaq, const DevInst *dev_
         merged_in = merge_out;
         if (plan.merge) fwd = !fwd;
     }
+    cur.fwd = fwd;
+    cur.merged_in = merged_in;
     return hipSuccess;
 }
 
@@ -656,16 +689,31 @@ lgt_status lgt_evolve(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, lg
     return evolve_fused(c, dt, cx, cz, order);
 }
 
-// fused form: the whole call as one chain of pass launches (tables staged once)
+// fused form: the whole call as one chain of pass launches.  The FP32 phase rows are
+// rounded and uploaded in chunks of doubling size, each chunk's launches enqueued as soon as
+// its rows are staged, so the device starts on the first steps while the host rounds the rest.
 static lgt_status evolve_fused(lgt_ctx *c, double dt, const std::vector<double> &cx,
                                const std::vector<double> &cz, lgt_order order)
 {
+    constexpr int kFirstChunk = 32;
     const Lattice &lat = c->lat;
     const int64_t count = (int64_t)cx.size();
     if (count > (1 << 24)) return fail(c, LGT_E_INVALID, "too many steps in one call");
+    const bool f32 = c->dtype == LGT_C64;
     StepTables st;
+    build_step_tables(lat.n_links, lat.n_plaq, dt, cx.data(), cz.data(), (int)count, order, st);
     Tables tb;
-    make_tables(lat, c->dtype, dt, cx, cz, order, st, tb);
+    std::vector<long double> gain;
+    if (f32) {
+        round_rot_f32(st, lat.n_links, tb.rf, gain);
+        tb.pf.assign((size_t)st.n_phase * (lat.n_plaq + 1), Cplx<float>{});
+    } else {
+        round_tables_f64(st, lat.n_plaq, tb.rd, tb.pd);
+    }
+    const size_t rot_row = f32 ? sizeof(RotParam<float>) : sizeof(RotParam<double>);
+    const size_t ph_row = (f32 ? sizeof(Cplx<float>) : sizeof(Cplx<double>)) * (lat.n_plaq + 1);
+    tb.rot_bytes = rot_row * (size_t)count;
+    tb.ph_bytes = ph_row * (size_t)st.n_phase;
     const size_t rb = align256(tb.rot_bytes), pb = align256(tb.ph_bytes);
     HIPCHK(c, ensure_stage(c, rb + pb + 256));
     HIPCHK(c, ensure_dev(c, &c->rot_dev, &c->rot_cap, rb));
@@ -678,8 +726,6 @@ static lgt_status evolve_fused(lgt_ctx *c, double dt, const std::vector<double> 
         c->inst_cap = 1;
     }
     char *stg = (char *)c->stage;
-    std::memcpy(stg, rot_ptr(tb, c->dtype), tb.rot_bytes);
-    std::memcpy(stg + rb, ph_ptr(tb, c->dtype), tb.ph_bytes);
     DevInst di{};
     di.psi = c->state;
     di.rot = c->rot_dev;
@@ -689,13 +735,37 @@ static lgt_status evolve_fused(lgt_ctx *c, double dt, const std::vector<double> 
     di.ph0 = 0;
     di.n_total = (int)count;
     std::memcpy(stg + rb + pb, &di, sizeof(di));
-    HIPCHK(c, hipMemcpyAsync(c->rot_dev, stg, tb.rot_bytes, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->ph_dev, stg + rb, tb.ph_bytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->inst_dev, stg + rb + pb, sizeof(DevInst), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipEventRecord(c->stage_free, c->stream));
     std::vector<uint8_t> forms;
     or_forms(st, forms);
-    HIPCHK(c, enqueue_fused(c, c->inst_dev, 1, (int)count, st.pre_phase, forms.data()));
+    const int n = lat.n_links, total = (int)count, pre = st.pre_phase;
+    // the single on-chip kernel runs every step at once
+    const bool chunked = !small_supported(c->dtype, n);
+    FusedCursor cur;
+    for (int j0 = 0, len = kFirstChunk; j0 < total; j0 += len, len *= 2) {
+        const int j1 = chunked ? (int)std::min<int64_t>(total, (int64_t)j0 + len) : total;
+        // rows read by the launches of steps [j0, j1): link layers j0 .. j1 (a merged launch
+        // ending the chunk also rotates step j1) and phase rows up to j1 - 1 + pre; the
+        // previous chunk already sent link layer j0
+        const int r0 = j0 == 0 ? 0 : j0 + 1, r1 = std::min(total, j1 + 1);
+        const int k0 = j0 == 0 ? 0 : j0 + pre, k1 = j1 + pre;
+        if (f32) round_phase_f32(st, lat.n_plaq, gain, k0, k1, tb.pf);
+        const char *rsrc = (const char *)rot_ptr(tb, c->dtype), *psrc = (const char *)ph_ptr(tb, c->dtype);
+        if (r1 > r0) {
+            const size_t off = rot_row * r0, len_b = rot_row * (size_t)(r1 - r0);
+            std::memcpy(stg + off, rsrc + off, len_b);
+            HIPCHK(c, hipMemcpyAsync((char *)c->rot_dev + off, stg + off, len_b, hipMemcpyHostToDevice, c->stream));
+        }
+        if (k1 > k0) {
+            const size_t off = ph_row * k0, len_b = ph_row * (size_t)(k1 - k0);
+            std::memcpy(stg + rb + off, psrc + off, len_b);
+            HIPCHK(c, hipMemcpyAsync((char *)c->ph_dev + off, stg + rb + off, len_b, hipMemcpyHostToDevice, c->stream));
+        }
+        HIPCHK(c, enqueue_fused_range(c->dtype, n, lat.n_plaq, c->inst_dev, 1, total, j0, j1,
+                                      pre ? 0 : -1, pre, forms.data(), c->plan, c->stream, c, cur));
+        if (!chunked) break;
+    }
+    HIPCHK(c, hipEventRecord(c->stage_free, c->stream));
     return LGT_OK;
 }
 

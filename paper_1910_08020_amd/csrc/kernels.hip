@@ -14,6 +14,7 @@
 // so P(base | r) = P(base) ^ P(r) with P(base) from byte tables in LDS and
 // P(r) from the per-link plaquette sets; the phase is table[popcount(P)].
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <type_traits>
 
@@ -1200,6 +1201,20 @@ hipError_t launch_low(int dtype, const DevInst *dev_inst, int n_inst, int n, int
     return hipGetLastError();
 }
 
+thread_local LaunchTiming *g_launch_timing = nullptr;
+
+template <typename K, typename... A>
+static void launch_timed(K kernel, dim3 g, dim3 b, hipStream_t st, A... args)
+{
+    LaunchTiming *lt = g_launch_timing;
+    if (!lt) {
+        hipLaunchKernelGGL(kernel, g, b, 0, st, args...);
+        return;
+    }
+    hipExtLaunchKernelGGL(kernel, g, b, 0, st, lt->used ? nullptr : lt->start, lt->stop, 0, args...);
+    lt->used = true;
+}
+
 template <typename T, int W, int ROWB>
 static hipError_t launch_pass_t(const DevInst *dev_inst, int n_inst, int n, int hb, int step,
                                 int pre, int post, int n_plaq, int forms, int merge, hipStream_t st)
@@ -1220,21 +1235,21 @@ static hipError_t launch_pass_t(const DevInst *dev_inst, int n_inst, int n, int 
         if (pre >= 0 || post < 0) return hipErrorInvalidValue;   // merged: one phase between
         const int fa = forms & 3, fb = (forms >> 2) & 3;
         if (fa & 1) {
-            hipLaunchKernelGGL((k_tile<T, W, ROWB, true, true, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+            launch_timed(k_tile<T, W, ROWB, true, true, true>, g, b, st, dev_inst, n, hb, step, -1, post, n_plaq);
             if (fb & 2)
-                hipLaunchKernelGGL((k_tile<T, W, ROWB, true, false, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+                launch_timed(k_tile<T, W, ROWB, true, false, true>, g, b, st, dev_inst, n, hb, step, -1, post, n_plaq);
         }
         if (fa & 2) {
-            hipLaunchKernelGGL((k_tile<T, W, ROWB, false, false, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+            launch_timed(k_tile<T, W, ROWB, false, false, true>, g, b, st, dev_inst, n, hb, step, -1, post, n_plaq);
             if (fb & 1)
-                hipLaunchKernelGGL((k_tile<T, W, ROWB, false, true, true>), g, b, 0, st, dev_inst, n, hb, step, -1, post, n_plaq);
+                launch_timed(k_tile<T, W, ROWB, false, true, true>, g, b, st, dev_inst, n, hb, step, -1, post, n_plaq);
         }
         return hipGetLastError();
     }
     if (forms & 1)
-        hipLaunchKernelGGL((k_tile<T, W, ROWB, true, true, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
+        launch_timed(k_tile<T, W, ROWB, true, true, false>, g, b, st, dev_inst, n, hb, step, pre, post, n_plaq);
     if (forms & 2)
-        hipLaunchKernelGGL((k_tile<T, W, ROWB, false, false, false>), g, b, 0, st, dev_inst, n, hb, step, pre, post, n_plaq);
+        launch_timed(k_tile<T, W, ROWB, false, false, false>, g, b, st, dev_inst, n, hb, step, pre, post, n_plaq);
     return hipGetLastError();
 }
 

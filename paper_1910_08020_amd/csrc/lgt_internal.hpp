@@ -72,6 +72,12 @@ void build_step_tables(int n_links, int n_plaq, double dt, const double *cx, con
 // nearby floats so the norm of one full step stays 1 to FP32 rounding.
 void round_tables_f32(const StepTables &in, int n_links, int n_plaq,
                       std::vector<RotParam<float>> &rot, std::vector<Cplx<float>> &ph);
+// The same rounding in pieces: every link layer (with its norm gain), then phase rows
+// [k0, k1) into a table sized for all rows.  Rows come out identical to the whole-table call.
+void round_rot_f32(const StepTables &in, int n_links, std::vector<RotParam<float>> &rot,
+                   std::vector<long double> &gain);
+void round_phase_f32(const StepTables &in, int n_plaq, const std::vector<long double> &gain,
+                     int k0, int k1, std::vector<Cplx<float>> &ph);
 void round_tables_f64(const StepTables &in, int n_plaq,
                       std::vector<RotParam<double>> &rot, std::vector<Cplx<double>> &ph);
 
@@ -139,6 +145,15 @@ hipError_t launch_high(int dtype, const DevInst *dev_inst, int n_inst, int n, in
 // 3 or 4 for complex128) and rotate index bits [hb, hb+h).
 // merge = 1: rotation of `step`, the phase `post`, then the rotation of step + 1 (pre = -1);
 // forms then holds the forms of step + 1 in bits 2-3.
+// Kernel-level timing of the tile launchers: while set, the launcher's first kernel
+// records `start` as it begins and every kernel records `stop` as it ends (timestamps of
+// the dispatch itself, so no extra stream packets sit between the kernels).
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool used = false;
+};
+extern thread_local LaunchTiming *g_launch_timing;
+
 hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, int low, int hb,
                        int h, int cb, int step, int pre, int post, int n_plaq, int forms,
                        int merge, hipStream_t st);
@@ -158,6 +173,15 @@ constexpr uint8_t kFormTan = 1, kFormCot = 2;
 hipError_t enqueue_fused_steps(int dtype, int n_links, int n_plaq, const DevInst *dev_inst,
                                int n_inst, int count, int pre_first, int post_off,
                                const uint8_t *forms, int plan, hipStream_t st, void *prof_ctx);
+// The same launches for steps [j_begin, j_end) of a count-step call, continued across
+// calls through `cur` (the pass order and whether the range starts inside a merged launch).
+struct FusedCursor {
+    bool fwd = true, merged_in = false;
+};
+hipError_t enqueue_fused_range(int dtype, int n, int n_plaq, const DevInst *dev_inst, int n_inst,
+                               int count, int j_begin, int j_end, int pre_first, int post_off,
+                               const uint8_t *forms, int plan_sel, hipStream_t st,
+                               void *prof_ctx, FusedCursor &cur);
 bool small_supported(int dtype, int n);
 // circuit-form gates
 hipError_t launch_gate_rx(int dtype, void *psi, int n, int q, double phi, hipStream_t st);

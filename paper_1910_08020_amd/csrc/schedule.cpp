@@ -128,20 +128,25 @@ static void round_pair_norm(double x, double y, double target2, float &fx, float
         }
 }
 
-void round_tables_f32(const StepTables &in, int n_links, int n_plaq,
-                      std::vector<RotParam<float>> &rot, std::vector<Cplx<float>> &ph)
+void round_rot_f32(const StepTables &in, int n_links, std::vector<RotParam<float>> &rot,
+                   std::vector<long double> &gain)
 {
-    const int np1 = n_plaq + 1;
     rot.resize(in.n_steps);
-    std::vector<long double> gain(in.n_steps);  // norm gain of the float link layer
+    gain.resize(in.n_steps);   // norm gain of the float link layer
     for (int j = 0; j < in.n_steps; ++j) {
         rot[j].u = (float)in.rot_u[j];
         rot[j].v = (float)in.rot_v[j];
         long double g = (long double)rot[j].u * rot[j].u + (long double)rot[j].v * rot[j].v;
         gain[j] = std::pow(g, (long double)n_links);
     }
-    ph.resize((size_t)in.n_phase * np1);
-    for (int k = 0; k < in.n_phase; ++k) {
+}
+
+void round_phase_f32(const StepTables &in, int n_plaq, const std::vector<long double> &gain,
+                     int k0, int k1, std::vector<Cplx<float>> &ph)
+{
+    const int np1 = n_plaq + 1;
+    if (ph.size() < (size_t)in.n_phase * np1) ph.resize((size_t)in.n_phase * np1);
+    for (int k = k0; k < k1; ++k) {
         // the phase after link layer j undoes that layer's gain exactly
         const int j = k - in.pre_phase;
         const long double target2 = (j >= 0) ? 1.0L / gain[j] : 1.0L;
@@ -157,6 +162,15 @@ void round_tables_f32(const StepTables &in, int n_links, int n_plaq,
                             ph[i].re, ph[i].im);
         }
     }
+}
+
+void round_tables_f32(const StepTables &in, int n_links, int n_plaq,
+                      std::vector<RotParam<float>> &rot, std::vector<Cplx<float>> &ph)
+{
+    std::vector<long double> gain;
+    round_rot_f32(in, n_links, rot, gain);
+    ph.assign((size_t)in.n_phase * (n_plaq + 1), Cplx<float>{});
+    round_phase_f32(in, n_plaq, gain, 0, in.n_phase, ph);
 }
 
 void round_tables_f64(const StepTables &in, int n_plaq, std::vector<RotParam<double>> &rot,

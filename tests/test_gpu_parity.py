@@ -462,3 +462,22 @@ def test_batch_with_mixed_forms_equals_single_runs():
         with gpu_ctx(d, L, C128) as ctx:
             lgt.lgt_evolve(ctx, s, SYM, lgt.LGT_FORM_FUSED, 0, n)
             assert np.array_equal(get_state(ctx), psi)
+
+
+@pytest.mark.parametrize("order", [TROT, SYM], ids=["trotter", "symmetric"])
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+def test_chunked_tables_equal_whole_table(order, dtype):
+    """A single-context run stages its tables in chunks of 32, 64, 128, ... steps; a batch
+    stages them whole.  Both must give the same state bit for bit, also across a change of
+    rotation form and with a chunk boundary inside a merged launch."""
+    d, L, n = 2, (3, 3), 300
+    s = lgt.make_schedule(0.05 * n, n, ramp=lgt.LGT_RAMP_COUPLING, g0=0.0, g1=40.0)
+    ctx = lgt.lgt_create(d, list(L), 1, dtype)
+    try:
+        lgt.lgt_batch_evolve([ctx], [s], [order], 0, n)
+        whole = get_state(ctx)
+    finally:
+        lgt.lgt_destroy(ctx)
+    with gpu_ctx(d, L, dtype) as c:
+        lgt.lgt_evolve(c, s, order, lgt.LGT_FORM_FUSED, 0, n)
+        assert np.array_equal(get_state(c), whole)
