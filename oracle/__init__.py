@@ -73,6 +73,16 @@ def lib():
         L.orc_rz.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double]
         L.orc_rx.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double]
         L.orc_plaq_gadget.argtypes = [ctypes.c_void_p, ctypes.c_int, _c_int_p, ctypes.c_double]
+        L.orc_cz.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_project_zero.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+        L.orc_anc_gadget.argtypes = [ctypes.c_void_p, ctypes.c_int, _c_int_p, ctypes.c_int,
+                                     ctypes.c_double]
+        L.orc_evolve_ancilla.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int_p,
+                                         ctypes.c_longlong, _c_dbl_p, _c_dbl_p, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int]
+        L.orc_evolve_ancilla.restype = ctypes.c_int
+        L.orc_prepare_ground_circuit.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                                 _c_int_p]
         L.orc_norm2.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_norm2.restype = ctypes.c_double
         L.orc_expect_z.argtypes = [ctypes.c_void_p, ctypes.c_int, _c_int_p, ctypes.c_int]
@@ -259,6 +269,64 @@ def rz(psi, N, q, phi):
 def rx(psi, N, q, phi):
     lib().orc_rx(_state_arg(psi, N), N, q, float(phi))
     return psi
+
+
+def cz_gate(psi, Ntot, a, b):
+    lib().orc_cz(_state_arg(psi, Ntot), Ntot, a, b)
+    return psi
+
+
+def project_zero(psi, Ntot, q):
+    lib().orc_project_zero(_state_arg(psi, Ntot), Ntot, q)
+    return psi
+
+
+# ---------------------------------------------------------------------------
+# one ancilla qubit on bit N of an (N+1)-qubit state (Sec. 2.2 eq. (ara), Sec. 2.3,
+# and the controlled evolution of Sec. 2.4)
+# ---------------------------------------------------------------------------
+def anc_gadget(psi, Ntot, links, a, theta):
+    """eq. (ara) for one plaquette: CNOTs from its links onto ancilla a, R_z^a(-2 theta),
+    the CNOTs in reverse order."""
+    ln = np.ascontiguousarray(links, dtype=np.int32)
+    lib().orc_anc_gadget(_state_arg(psi, Ntot), Ntot, _ip(ln), int(a), float(theta))
+    return psi
+
+
+def with_ancilla(psi_lattice: np.ndarray, anc: int = 0) -> np.ndarray:
+    """|psi> (x) |anc>_a with the ancilla on the new top bit."""
+    out = np.zeros(2 * psi_lattice.size, dtype=np.complex128)
+    off = psi_lattice.size if anc else 0
+    out[off:off + psi_lattice.size] = psi_lattice
+    return out
+
+
+def evolve_ancilla(psi: np.ndarray, lat: Lattice, dt: float, cx, cz, order: int,
+                   controlled: bool = False) -> np.ndarray:
+    """In-place evolution of an (N+1)-qubit state in the ancilla circuit form: eq. (ara)
+    for each plaquette, R_x on each link, in the orders of eq. (a) / eq. (s).  With
+    `controlled`, every R_x sits between two CZ(ancilla, link): the ancilla then sets the
+    direction of time for both parts, the U(t) of the phase-estimation passage."""
+    N = lat.N
+    cx = np.ascontiguousarray(cx, dtype=np.float64)
+    cz = np.ascontiguousarray(cz, dtype=np.float64)
+    if cx.shape != cz.shape:
+        raise ValueError("cx and cz must have one entry per step")
+    rc = lib().orc_evolve_ancilla(_state_arg(psi, N + 1), N, lat.n_plaq, _ip(lat.plaq),
+                                  len(cx), _dp(cx), _dp(cz), float(dt), int(order),
+                                  1 if controlled else 0)
+    if rc != 0:
+        raise ValueError("bad order")
+    return psi
+
+
+def prepare_ground_circuit(lat: Lattice) -> np.ndarray:
+    """Sec. 2.3 with the ancilla: |+>^N |0>_a, then for every plaquette CNOTs onto the
+    ancilla, a measurement selecting ancilla |0>, CNOTs back; normalised at the end."""
+    N = lat.N
+    psi = with_ancilla(plus_state(N), 0)
+    lib().orc_prepare_ground_circuit(_state_arg(psi, N + 1), N, lat.n_plaq, _ip(lat.plaq))
+    return psi / np.sqrt(norm2(psi, N + 1))
 
 
 # ---------------------------------------------------------------------------

@@ -347,6 +347,97 @@ int orc_evolve_circuit(double complex *psi, int N, int n_plaq, const int *plaq,
 }
 
 /* ------------------------------------------------------------------ */
+/* circuits with one ancilla qubit a (Sec. 2.2, eq. (ara); Sec. 2.3;    */
+/* the controlled evolution U(t) of Sec. 2.4).  The state has N + 1     */
+/* qubits; the callers put the ancilla on bit N.                        */
+/* ------------------------------------------------------------------ */
+
+/* controlled-Z: amplitude sign flips where qubits a and b are both |1> */
+void orc_cz(double complex *psi, int Ntot, int a, int b)
+{
+    uint64_t dim = 1ull << Ntot, m = (1ull << a) | (1ull << b);
+    for (uint64_t i = 0; i < dim; ++i)
+        if ((i & m) == m) psi[i] = -psi[i];
+}
+
+/* measurement of qubit q with outcome |0> selected: the |1> half is dropped
+   (the caller renormalises) */
+void orc_project_zero(double complex *psi, int Ntot, int q)
+{
+    uint64_t dim = 1ull << Ntot, bit = 1ull << q;
+    for (uint64_t i = 0; i < dim; ++i)
+        if (i & bit) psi[i] = 0;
+}
+
+/*
+ * eq. (ara): A^-1 R_z^a(-2 theta) A with A the product of CNOT(l -> a) over the four
+ * plaquette links.  A writes the plaquette parity into the ancilla, R_z^a(-2 theta)
+ * multiplies ancilla |0> by e^{+i theta} and |1> by e^{-i theta}, and the reversed
+ * CNOTs restore the ancilla.  Ancilla |0>: exp(+i theta U_p) = exp(-i theta Z_p);
+ * ancilla |1>: the opposite sign, i.e. the time-reversed plaquette evolution.
+ */
+void orc_anc_gadget(double complex *psi, int Ntot, const int *links, int a, double theta)
+{
+    for (int k = 0; k < 4; ++k) orc_cnot(psi, Ntot, links[k], a);
+    orc_rz(psi, Ntot, a, -2.0 * theta);
+    for (int k = 3; k >= 0; --k) orc_cnot(psi, Ntot, links[k], a);
+}
+
+/* link layer exp(+i alpha sum sigma^x); with `controlled`, each R_x sits between two
+   CZ(a, l), which turns it into R_x of the opposite angle when the ancilla is |1>
+   (Z R_x(phi) Z = R_x(-phi)): the direction of time follows the ancilla */
+static void anc_x(double complex *psi, int N, int a, double alpha, int controlled)
+{
+    for (int q = 0; q < N; ++q) {
+        if (controlled) orc_cz(psi, N + 1, a, q);
+        orc_rx(psi, N + 1, q, -2.0 * alpha);
+        if (controlled) orc_cz(psi, N + 1, a, q);
+    }
+}
+
+static void anc_z(double complex *psi, int N, int a, int n_plaq, const int *plaq, double theta)
+{
+    for (int p = 0; p < n_plaq; ++p) orc_anc_gadget(psi, N + 1, plaq + 4 * p, a, theta);
+}
+
+/* the orders of orc_evolve with the ancilla gadget for every plaquette; the ancilla is
+   bit N of the (N+1)-qubit state */
+int orc_evolve_ancilla(double complex *psi, int N, int n_plaq, const int *plaq,
+                       long long n_steps, const double *cx, const double *cz,
+                       double dt, int order, int controlled)
+{
+    if (order != 1 && order != 2) return -1;
+    const int a = N;
+    for (long long j = 0; j < n_steps; ++j) {
+        if (order == 1) {
+            anc_x(psi, N, a, dt * cx[j], controlled);
+            anc_z(psi, N, a, n_plaq, plaq, dt * cz[j]);
+        } else {
+            anc_z(psi, N, a, n_plaq, plaq, 0.5 * dt * cz[j]);
+            anc_x(psi, N, a, dt * cx[j], controlled);
+            anc_z(psi, N, a, n_plaq, plaq, 0.5 * dt * cz[j]);
+        }
+    }
+    return 0;
+}
+
+/*
+ * Sec. 2.3: from |+>^N |0>_a, for each plaquette the four CNOT(l -> a) put its parity on
+ * the ancilla, the ancilla is measured with outcome |0> (even parity, U_p = +1), and four
+ * more CNOTs return it to |0>.  The product of the projections is left unnormalised.
+ */
+void orc_prepare_ground_circuit(double complex *psi, int N, int n_plaq, const int *plaq)
+{
+    const int a = N;
+    for (int p = 0; p < n_plaq; ++p) {
+        const int *l = plaq + 4 * p;
+        for (int k = 0; k < 4; ++k) orc_cnot(psi, N + 1, l[k], a);
+        orc_project_zero(psi, N + 1, a);
+        for (int k = 3; k >= 0; --k) orc_cnot(psi, N + 1, l[k], a);
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* pseudo-measurement (Sec. 2.4): sums over all basis states            */
 /* Sums run sequentially in ascending b with an extended-precision      */
 /* (long double) accumulator, so that 2^24-term sums stay far below     */
