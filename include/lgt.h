@@ -59,12 +59,29 @@ typedef enum { LGT_ORDER_TROTTER = 1, LGT_ORDER_SYMMETRIC = 2 } lgt_order;
  * CIRCUIT: one full-state pass per gate, as in eq. (ara)
  * (CNOT ladder onto the last plaquette link, R_z, inverse ladder) and the
  * R_x link layer of Sec. 2.2. */
-typedef enum { LGT_FORM_FUSED = 0, LGT_FORM_CIRCUIT = 1 } lgt_form;
+/* ANCILLA: eq. (ara) itself: for every plaquette the CNOTs from its four links onto the
+ * ancilla qubit, R_z^a(-2 theta) on the ancilla and the CNOTs in reverse order, and R_x on
+ * every link.  With the ancilla in |0> this is the forward evolution; in |1> the plaquette
+ * part runs backwards in time (the remark after eq. (ara)).
+ * CONTROLLED: the same with every R_x between two CZ(ancilla, link), so that the ancilla
+ * sets the direction of time of the whole step: |0><0| (x) U(t) + |1><1| (x) U(-t), the
+ * controlled evolution that phase estimation needs (Sec. 2.4).
+ * Both need a context from lgt_create_ancilla; such a context runs these two forms only. */
+typedef enum {
+    LGT_FORM_FUSED = 0,
+    LGT_FORM_CIRCUIT = 1,
+    LGT_FORM_ANCILLA = 2,
+    LGT_FORM_CONTROLLED = 3
+} lgt_form;
 
 typedef enum {
     LGT_INIT_PLUS = 0,     /* |+>^N: Hadamard on every link (Sec. 2.3)              */
     LGT_INIT_ZGROUND = 1,  /* prod_p P_p |+>^N normalised: every U_p = +1 (Sec. 2.3) */
-    LGT_INIT_BASIS = 2     /* computational basis state |basis_index>                */
+    LGT_INIT_BASIS = 2,    /* computational basis state |basis_index>                */
+    LGT_INIT_ZGROUND_CIRCUIT = 3  /* ancilla contexts: |+>^N |0>_a, then for every plaquette
+                                     CNOTs onto the ancilla, a measurement keeping ancilla
+                                     |0>, CNOTs back (Sec. 2.3); normalised at the end.
+                                     Equals ZGROUND (x) |0>_a                               */
 } lgt_init;
 
 /* ---------------------------------------------------------------------------
@@ -92,6 +109,17 @@ lgt_status lgt_create(int d, const int *L, int periodic, lgt_dtype dtype, lgt_ct
 lgt_status lgt_create_ex(int d, const int *L, int periodic, lgt_dtype dtype,
                          void *dev_buf, size_t bytes, void *stream, lgt_ctx **out);
 
+/*
+ * lgt_create_ancilla: as lgt_create, with one ancilla qubit a = bit N_l of the amplitude
+ * index on top of the links (2^(N_l+1) amplitudes; the lattice part of every index keeps
+ * its layout).  lgt_reset puts the lattice in the requested state and the ancilla in |0>
+ * (LGT_INIT_BASIS takes an (N_l+1)-bit index).  Such a context evolves with
+ * LGT_FORM_ANCILLA / LGT_FORM_CONTROLLED; lgt_measure, lgt_sample, lgt_apply_pauli and
+ * lgt_apply_gate act on all N_l + 1 qubits (masks may name bit N_l).  Scans, batches,
+ * lgt_tune and LGT_OBS_XDOS give LGT_E_UNSUPPORTED.
+ */
+lgt_status lgt_create_ancilla(int d, const int *L, int periodic, lgt_dtype dtype, lgt_ctx **out);
+
 lgt_status lgt_destroy(lgt_ctx *ctx);
 
 typedef struct {
@@ -105,6 +133,7 @@ typedef struct {
     const int32_t *plaq_links;    /* [n_plaq*4] links in the order l(s,mu), l(s+e_mu,nu), l(s+e_nu,mu), l(s,nu) */
     const uint64_t *star_masks;   /* [n_sites]  links ending at each site (Gauss law G_i) */
     const uint32_t *link_plaqs;   /* [n_links]  plaquettes containing each link, bit p   */
+    int n_qubits;                 /* n_links, plus 1 for an ancilla context              */
 } lgt_info_t;
 
 /* Host pointers in *out stay valid until lgt_destroy. */
@@ -232,6 +261,22 @@ lgt_status lgt_measure(lgt_ctx *ctx, const lgt_observable *obs, double *out, siz
  * E_INVALID for masks with bits at or beyond N_l.
  */
 lgt_status lgt_apply_pauli(lgt_ctx *ctx, uint64_t xmask, uint64_t zmask);
+
+/*
+ * lgt_apply_gate: one gate of the circuits of Sec. 2.2 - 2.4 on qubit q0 (and q1), any
+ * qubit of the context including the ancilla: H (Hadamard), X, RX / RZ
+ * (exp(-i sigma angle / 2)), CNOT (control q0, target q1), CZ.  One full-state pass,
+ * stream-ordered.  E_INVALID for qubits out of range or q0 == q1 in a two-qubit gate.
+ */
+typedef enum {
+    LGT_GATE_H = 0,
+    LGT_GATE_X = 1,
+    LGT_GATE_RX = 2,
+    LGT_GATE_RZ = 3,
+    LGT_GATE_CNOT = 4,
+    LGT_GATE_CZ = 5
+} lgt_gate;
+lgt_status lgt_apply_gate(lgt_ctx *ctx, lgt_gate gate, int q0, int q1, double angle);
 
 /*
  * lgt_scan: the stepwise adiabatic evolution of Sec. 2.2, paused for measurement after every

@@ -59,10 +59,14 @@ struct lgt_ctx {
     int64_t prof_launches[KF_COUNT] = {0};
     double prof_ms[KF_COUNT] = {0};
     int plan = 0;   // pass plan code (plan_passes), 0 = built-in rule
+    int n_anc = 0;  // 1: one ancilla qubit on bit N_l above the links
     std::string err;
 };
 
 namespace {
+
+// qubits of the state: the links, plus the ancilla of an ancilla context
+int nq(const lgt_ctx *c) { return c->lat.n_links + c->n_anc; }
 
 constexpr int kMaxPartialBlocks = 2048;
 constexpr int kPartialWidth = kMaxPlaq + 1;
@@ -415,7 +419,7 @@ static void or_forms(const StepTables &st, std::vector<uint8_t> &forms)
 }
 
 static lgt_status create_common(int d, const int *L, int periodic, lgt_dtype dtype, void *buf,
-                                size_t bytes, void *stream, lgt_ctx **out)
+                                size_t bytes, void *stream, int n_anc, lgt_ctx **out)
 {
     if (!out) return fail(nullptr, LGT_E_INVALID, "null output pointer");
     *out = nullptr;
@@ -433,7 +437,8 @@ static lgt_status create_common(int d, const int *L, int periodic, lgt_dtype dty
     if (!c) return fail(nullptr, LGT_E_OOM, "host allocation failed");
     c->lat = std::move(lat);
     c->dtype = dtype;
-    c->state_bytes = ((size_t)1 << c->lat.n_links) * elem_bytes(dtype);
+    c->n_anc = n_anc;
+    c->state_bytes = ((size_t)1 << nq(c.get())) * elem_bytes(dtype);
     if (hipGetDevice(&c->device) != hipSuccess) return fail(nullptr, LGT_E_DEVICE, "no HIP device");
     if (buf) {
         if (bytes < c->state_bytes) return fail(nullptr, LGT_E_INVALID, "external buffer too small");
@@ -486,14 +491,19 @@ extern "C" {
 
 lgt_status lgt_create(int d, const int *L, int periodic, lgt_dtype dtype, lgt_ctx **out)
 {
-    return create_common(d, L, periodic, dtype, nullptr, 0, nullptr, out);
+    return create_common(d, L, periodic, dtype, nullptr, 0, nullptr, 0, out);
+}
+
+lgt_status lgt_create_ancilla(int d, const int *L, int periodic, lgt_dtype dtype, lgt_ctx **out)
+{
+    return create_common(d, L, periodic, dtype, nullptr, 0, nullptr, 1, out);
 }
 
 lgt_status lgt_create_ex(int d, const int *L, int periodic, lgt_dtype dtype, void *dev_buf,
                          size_t bytes, void *stream, lgt_ctx **out)
 {
     if (!dev_buf) return fail(nullptr, LGT_E_INVALID, "null device buffer");
-    return create_common(d, L, periodic, dtype, dev_buf, bytes, stream, out);
+    return create_common(d, L, periodic, dtype, dev_buf, bytes, stream, 0, out);
 }
 
 lgt_status lgt_destroy(lgt_ctx *c)
@@ -527,6 +537,7 @@ lgt_status lgt_info(const lgt_ctx *c, lgt_info_t *o)
     o->d = l.d;
     for (int i = 0; i < 3; ++i) o->L[i] = i < l.d ? l.L[i] : 1;
     o->n_links = l.n_links;
+    o->n_qubits = nq(c);
     o->n_plaq = l.n_plaq;
     o->n_sites = l.n_sites;
     o->dtype = (lgt_dtype)c->dtype;
@@ -587,17 +598,65 @@ lgt_status lgt_apply_pauli(lgt_ctx *c, uint64_t xmask, uint64_t zmask)
 {
     lgt_status s = check_ctx(c);
     if (s) return s;
-    const int n = c->lat.n_links;
+    const int n = nq(c);
     if ((xmask >> n) || (zmask >> n)) return fail(c, LGT_E_INVALID, "mask has bits beyond N");
     HIPCHK(c, launch_pauli(c->dtype, c->state, n, xmask, zmask, c->stream));
     return LGT_OK;
 }
+
+lgt_status lgt_apply_gate(lgt_ctx *c, lgt_gate gate, int q0, int q1, double angle)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    const int n = nq(c);
+    const bool two = gate == LGT_GATE_CNOT || gate == LGT_GATE_CZ;
+    if (q0 < 0 || q0 >= n || (two && (q1 < 0 || q1 >= n || q1 == q0)))
+        return fail(c, LGT_E_INVALID, "qubit index out of range");
+    switch (gate) {
+    case LGT_GATE_H:
+        HIPCHK(c, timed(c, KF_GATE_H, [&] { return launch_gate_h(c->dtype, c->state, n, q0, c->stream); }));
+        break;
+    case LGT_GATE_X:
+        HIPCHK(c, launch_pauli(c->dtype, c->state, n, 1ull << q0, 0, c->stream));
+        break;
+    case LGT_GATE_RX:
+        HIPCHK(c, timed(c, KF_GATE_RX, [&] { return launch_gate_rx(c->dtype, c->state, n, q0, angle, c->stream); }));
+        break;
+    case LGT_GATE_RZ:
+        HIPCHK(c, timed(c, KF_GATE_RZ, [&] { return launch_gate_rz(c->dtype, c->state, n, q0, angle, c->stream); }));
+        break;
+    case LGT_GATE_CNOT:
+        HIPCHK(c, timed(c, KF_GATE_CNOT, [&] { return launch_gate_cnot(c->dtype, c->state, n, q0, q1, c->stream); }));
+        break;
+    case LGT_GATE_CZ:
+        HIPCHK(c, timed(c, KF_GATE_CZ, [&] { return launch_gate_cz(c->dtype, c->state, n, q0, q1, c->stream); }));
+        break;
+    default:
+        return fail(c, LGT_E_INVALID, "unknown gate");
+    }
+    return LGT_OK;
+}
+
+static lgt_status ground_circuit(lgt_ctx *c);
 
 lgt_status lgt_reset(lgt_ctx *c, lgt_init init, uint64_t basis_index)
 {
     lgt_status s = check_ctx(c);
     if (s) return s;
     const int n = c->lat.n_links;
+    if (init == LGT_INIT_BASIS && (basis_index >> nq(c)))
+        return fail(c, LGT_E_INVALID, "basis index >= 2^(number of qubits)");
+    if (init == LGT_INIT_BASIS && c->n_anc) {
+        HIPCHK(c, timed(c, KF_INIT, [&] {
+            return launch_init(c->dtype, c->state, nq(c), init, basis_index, 0.0, c->ptab_dev, c->stream);
+        }));
+        return LGT_OK;
+    }
+    if (init == LGT_INIT_ZGROUND_CIRCUIT) {
+        if (!c->n_anc) return fail(c, LGT_E_UNSUPPORTED, "the projection circuit needs an ancilla context");
+        if ((s = lgt_reset(c, LGT_INIT_PLUS, 0))) return s;
+        return ground_circuit(c);
+    }
     double amp = 0;
     if (init == LGT_INIT_PLUS) {
         amp = std::ldexp(1.0, -n / 2) * ((n & 1) ? std::sqrt(0.5) : 1.0);
@@ -621,6 +680,11 @@ lgt_status lgt_reset(lgt_ctx *c, lgt_init init, uint64_t basis_index)
     } else {
         return fail(c, LGT_E_INVALID, "bad init kind");
     }
+    // an ancilla context: the lattice state on the ancilla-|0> half, the other half cleared
+    if (c->n_anc)
+        HIPCHK(c, timed(c, KF_PROJECT, [&] {
+            return launch_project_scale(c->dtype, c->state, nq(c), 1ull << n, 1.0, c->stream);
+        }));
     HIPCHK(c, timed(c, KF_INIT, [&] {
         return launch_init(c->dtype, c->state, n, init, basis_index, amp, c->ptab_dev, c->stream);
     }));
@@ -637,8 +701,13 @@ lgt_status lgt_evolve(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, lg
     if (s) return s;
     if (order != LGT_ORDER_TROTTER && order != LGT_ORDER_SYMMETRIC)
         return fail(c, LGT_E_INVALID, "bad order");
-    if (form != LGT_FORM_FUSED && form != LGT_FORM_CIRCUIT)
+    if (form != LGT_FORM_FUSED && form != LGT_FORM_CIRCUIT && form != LGT_FORM_ANCILLA &&
+        form != LGT_FORM_CONTROLLED)
         return fail(c, LGT_E_UNSUPPORTED, "unknown form");
+    const bool anc_form = form == LGT_FORM_ANCILLA || form == LGT_FORM_CONTROLLED;
+    if (anc_form != (c->n_anc == 1))
+        return fail(c, LGT_E_UNSUPPORTED, anc_form ? "this form needs an ancilla context"
+                                                   : "an ancilla context runs the ancilla forms only");
     double dt = 0;
     std::vector<double> cx, cz;
     std::string why = schedule_coeffs(sched, first_step, count, dt, cx, cz);
@@ -647,6 +716,58 @@ lgt_status lgt_evolve(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, lg
     const Lattice &lat = c->lat;
     const int n = lat.n_links;
     StepTables st;
+    if (anc_form) {
+        // eq. (ara) for every plaquette with the ancilla (bit n) as the CNOT target; the
+        // symmetric order merges neighbouring half steps like the other forms
+        build_step_tables(n, lat.n_plaq, dt, cx.data(), cz.data(), (int)count, order, st);
+        const int nt = nq(c), a = n;
+        const bool ctl = form == LGT_FORM_CONTROLLED;
+        std::vector<double> theta(st.n_phase);
+        if (order == LGT_ORDER_TROTTER) {
+            for (int64_t j = 0; j < count; ++j) theta[j] = dt * cz[j];
+        } else {
+            theta[0] = 0.5 * dt * cz[0];
+            for (int64_t j = 0; j < count; ++j)
+                theta[j + 1] = (j + 1 < count) ? 0.5 * dt * (cz[j] + cz[j + 1]) : 0.5 * dt * cz[j];
+        }
+        auto gadgets = [&](double th) -> hipError_t {
+            for (int p = 0; p < lat.n_plaq; ++p) {
+                const int32_t *l = &lat.plaq_links[4 * p];
+                for (int k = 0; k < 4; ++k) {
+                    hipError_t e = timed(c, KF_GATE_CNOT, [&] { return launch_gate_cnot(c->dtype, c->state, nt, l[k], a, c->stream); });
+                    if (e != hipSuccess) return e;
+                }
+                hipError_t e = timed(c, KF_GATE_RZ, [&] { return launch_gate_rz(c->dtype, c->state, nt, a, -2.0 * th, c->stream); });
+                if (e != hipSuccess) return e;
+                for (int k = 3; k >= 0; --k) {
+                    e = timed(c, KF_GATE_CNOT, [&] { return launch_gate_cnot(c->dtype, c->state, nt, l[k], a, c->stream); });
+                    if (e != hipSuccess) return e;
+                }
+            }
+            return hipSuccess;
+        };
+        // R_x on every link; controlled: between two CZ(ancilla, link), which reverses the
+        // rotation on the ancilla-|1> half
+        auto links = [&](double alpha) -> hipError_t {
+            for (int q = 0; q < n; ++q) {
+                hipError_t e = hipSuccess;
+                if (ctl) e = timed(c, KF_GATE_CZ, [&] { return launch_gate_cz(c->dtype, c->state, nt, a, q, c->stream); });
+                if (e == hipSuccess)
+                    e = timed(c, KF_GATE_RX, [&] { return launch_gate_rx(c->dtype, c->state, nt, q, -2.0 * alpha, c->stream); });
+                if (e == hipSuccess && ctl)
+                    e = timed(c, KF_GATE_CZ, [&] { return launch_gate_cz(c->dtype, c->state, nt, a, q, c->stream); });
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        };
+        const int pre = st.pre_phase;
+        if (pre) HIPCHK(c, gadgets(theta[0]));
+        for (int64_t j = 0; j < count; ++j) {
+            HIPCHK(c, links(dt * cx[j]));
+            HIPCHK(c, gadgets(theta[j + pre]));
+        }
+        return LGT_OK;
+    }
     if (form == LGT_FORM_CIRCUIT) {
         // one pass per gate; the symmetric order merges neighbouring half steps
         // like the fused path (rewritten product after eq. (s))
@@ -772,7 +893,7 @@ static lgt_status evolve_fused(lgt_ctx *c, double dt, const std::vector<double> 
 static lgt_status reduce_masks(lgt_ctx *c, bool flip, const uint64_t *masks, int n_masks,
                                std::vector<long double> &out)
 {
-    const int n = c->lat.n_links;
+    const int n = nq(c);
     const int chunk = flip ? kFlipChunk : kMaskChunk;
     const int g = reduce_blocks(n);
     out.assign(n_masks, 0.0L);
@@ -806,6 +927,30 @@ static lgt_status norm_of(lgt_ctx *c, long double &nrm)
     return LGT_OK;
 }
 
+// Sec. 2.3 with the ancilla (bit N): for every plaquette, CNOTs from its links onto the
+// ancilla, a measurement that keeps ancilla |0> (even parity, U_p = +1), CNOTs back; the
+// product of the projections is normalised at the end.
+static lgt_status ground_circuit(lgt_ctx *c)
+{
+    const Lattice &lat = c->lat;
+    const int nt = nq(c), a = lat.n_links;
+    for (int p = 0; p < lat.n_plaq; ++p) {
+        const int32_t *l = &lat.plaq_links[4 * p];
+        for (int k = 0; k < 4; ++k)
+            HIPCHK(c, timed(c, KF_GATE_CNOT, [&] { return launch_gate_cnot(c->dtype, c->state, nt, l[k], a, c->stream); }));
+        HIPCHK(c, timed(c, KF_PROJECT, [&] { return launch_project_scale(c->dtype, c->state, nt, 1ull << a, 1.0, c->stream); }));
+        for (int k = 3; k >= 0; --k)
+            HIPCHK(c, timed(c, KF_GATE_CNOT, [&] { return launch_gate_cnot(c->dtype, c->state, nt, l[k], a, c->stream); }));
+    }
+    long double nrm = 0;
+    lgt_status s = norm_of(c, nrm);
+    if (s) return s;
+    if (!(nrm > 0)) return fail(c, LGT_E_STATE, "projection left a zero state");
+    const double scale = (double)(1.0L / std::sqrt(nrm));
+    HIPCHK(c, timed(c, KF_PROJECT, [&] { return launch_project_scale(c->dtype, c->state, nt, 0, scale, c->stream); }));
+    return LGT_OK;
+}
+
 lgt_status lgt_measure(lgt_ctx *c, const lgt_observable *obs, double *out, size_t out_len)
 {
     lgt_status s = check_ctx(c);
@@ -821,7 +966,7 @@ lgt_status lgt_measure(lgt_ctx *c, const lgt_observable *obs, double *out, size_
     case LGT_OBS_X:
         if (obs->n_masks < 1 || !obs->masks) return fail(c, LGT_E_INVALID, "need masks");
         for (int i = 0; i < obs->n_masks; ++i)
-            if (obs->masks[i] >> lat.n_links) return fail(c, LGT_E_INVALID, "mask has bits beyond N");
+            if (obs->masks[i] >> nq(c)) return fail(c, LGT_E_INVALID, "mask has bits beyond the qubits");
         masks.assign(obs->masks, obs->masks + obs->n_masks);
         flip = obs->kind == LGT_OBS_X;
         need = masks.size();
@@ -848,9 +993,9 @@ lgt_status lgt_measure(lgt_ctx *c, const lgt_observable *obs, double *out, size_
     }
     if (!(nrm > 0)) return fail(c, LGT_E_STATE, "state has zero norm");
     if (obs->kind == LGT_OBS_ZDOS) {
-        const int g = reduce_blocks(lat.n_links);
+        const int g = reduce_blocks(nq(c));
         HIPCHK(c, timed(c, KF_RED_DOS, [&] {
-            return launch_reduce_dos(c->dtype, c->state, lat.n_links, c->ptab_dev, lat.n_plaq, c->partials, c->stream);
+            return launch_reduce_dos(c->dtype, c->state, nq(c), c->ptab_dev, lat.n_plaq, c->partials, c->stream);
         }));
         HIPCHK(c, hipMemcpyAsync(c->partials_host.data(), c->partials, sizeof(double) * g * kPartialWidth,
                                  hipMemcpyDeviceToHost, c->stream));
@@ -865,6 +1010,7 @@ lgt_status lgt_measure(lgt_ctx *c, const lgt_observable *obs, double *out, size_
     if (obs->kind == LGT_OBS_XDOS) {
         // sigma^x basis: Hadamard on every link of a copy, then the popcount histogram
         if (lat.n_links > kMaxPlaq) return fail(c, LGT_E_UNSUPPORTED, "X-DOS supports <= 32 links");
+        if (c->n_anc) return fail(c, LGT_E_UNSUPPORTED, "X-DOS of an ancilla context");
         void *tmp = nullptr;
         if (hipMalloc(&tmp, c->state_bytes) != hipSuccess) return fail(c, LGT_E_OOM, "X-DOS buffer");
         hipError_t e = hipMemcpyAsync(tmp, c->state, c->state_bytes, hipMemcpyDeviceToDevice, c->stream);
@@ -917,6 +1063,7 @@ lgt_status lgt_scan(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, int6
         return fail(c, LGT_E_INVALID, "bad order");
     if (substeps < 1 || n_points < 1 || n_masks < 0 || n_masks > 32 || (n_masks > 0 && !masks))
         return fail(c, LGT_E_INVALID, "bad scan sizes");
+    if (c->n_anc) return fail(c, LGT_E_UNSUPPORTED, "scans run the fused form: not on an ancilla context");
     const Lattice &lat = c->lat;
     const int n = lat.n_links;
     for (int i = 0; i < n_masks; ++i)
@@ -1066,7 +1213,7 @@ lgt_status lgt_sample(lgt_ctx *c, uint64_t n_shots, uint64_t seed, uint64_t *out
     if (s) return s;
     if (!out) return fail(c, LGT_E_INVALID, "null output");
     if (n_shots < 1 || n_shots > (1ull << 26)) return fail(c, LGT_E_INVALID, "n_shots out of range");
-    const int n = c->lat.n_links;
+    const int n = nq(c);
     const size_t nb = (size_t)1 << (n - sample_block_bits(n));
     double *sums = nullptr, *prefix = nullptr;
     uint64_t *dev_out = nullptr;
@@ -1115,7 +1262,7 @@ lgt_status lgt_copy_state(lgt_ctx *dst, lgt_ctx *src)
 {
     lgt_status s = check_ctx(dst);
     if (s) return s;
-    if (!src || src->dtype != dst->dtype || src->lat.d != dst->lat.d ||
+    if (!src || src->dtype != dst->dtype || src->lat.d != dst->lat.d || src->n_anc != dst->n_anc ||
         std::memcmp(src->lat.L, dst->lat.L, sizeof src->lat.L) != 0 || src->device != dst->device)
         return fail(dst, LGT_E_INVALID, "copy needs contexts of one lattice, dtype and device");
     if (src == dst) return LGT_OK;
@@ -1201,6 +1348,7 @@ lgt_status lgt_tune(lgt_ctx *c, int steps)
     lgt_status s = check_ctx(c);
     if (s) return s;
     if (steps < 1 || steps > 1024) return fail(c, LGT_E_INVALID, "steps must be in [1, 1024]");
+    if (c->n_anc) return fail(c, LGT_E_UNSUPPORTED, "the ancilla forms have no pass plan to tune");
     const Lattice &lat = c->lat;
     const int n = lat.n_links;
     if (small_supported(c->dtype, n)) return LGT_OK;   // one on-chip kernel: nothing to choose
@@ -1281,6 +1429,7 @@ lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule
         if (!c || c->dtype != c0->dtype || c->lat.d != c0->lat.d ||
             std::memcmp(c->lat.L, c0->lat.L, sizeof c->lat.L) != 0 || c->device != c0->device)
             return fail(nullptr, LGT_E_INVALID, "batch contexts must share lattice, dtype and device");
+        if (c->n_anc) return fail(nullptr, LGT_E_UNSUPPORTED, "batches run the fused form: no ancilla contexts");
         if (orders[i] != LGT_ORDER_TROTTER && orders[i] != LGT_ORDER_SYMMETRIC)
             return fail(nullptr, LGT_E_INVALID, "bad order");
         if (orders[i] != orders[0])

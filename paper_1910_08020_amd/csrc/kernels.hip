@@ -940,6 +940,41 @@ __global__ void k_gate_rz(cplx_t<T> *psi, int n, int q, cplx_t<T> e0, cplx_t<T> 
         psi[b] = cmul(psi[b], ((b >> q) & 1) ? e1 : e0);
 }
 
+// controlled-Z: sign flip where qubits a and b are both |1>
+template <typename T>
+__global__ void k_gate_cz(cplx_t<T> *psi, int n, uint64_t both)
+{
+    const uint64_t dim = 1ull << n;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < dim;
+         b += (uint64_t)gridDim.x * blockDim.x)
+        if ((b & both) == both) {
+            cplx_t<T> a = psi[b];
+            a.x = -a.x;
+            a.y = -a.y;
+            psi[b] = a;
+        }
+}
+
+// measurement with outcome |0> on every qubit of zero_mask (those amplitudes dropped),
+// the rest multiplied by `scale`
+template <typename T>
+__global__ void k_project_scale(cplx_t<T> *psi, int n, uint64_t zero_mask, T scale)
+{
+    const uint64_t dim = 1ull << n;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < dim;
+         b += (uint64_t)gridDim.x * blockDim.x) {
+        cplx_t<T> a = psi[b];
+        if (b & zero_mask) {
+            a.x = 0;
+            a.y = 0;
+        } else {
+            a.x *= scale;
+            a.y *= scale;
+        }
+        psi[b] = a;
+    }
+}
+
 template <typename T>
 __global__ void k_gate_cnot(cplx_t<T> *psi, int n, int c, int t)
 {
@@ -1162,7 +1197,7 @@ const char *kernel_family_name(int kf)
     static const char *names[KF_COUNT] = {"init", "pass_low", "pass_high", "phase", "small",
                                           "gate_rx", "gate_rz", "gate_cnot", "reduce_diag",
                                           "reduce_flip", "reduce_dos", "sample", "tile_low",
-                                          "tile_high", "gate_h"};
+                                          "tile_high", "gate_h", "gate_cz", "project"};
     return (kf >= 0 && kf < KF_COUNT) ? names[kf] : "?";
 }
 
@@ -1501,6 +1536,31 @@ hipError_t launch_gate_h(int dtype, void *psi, int n, int q, hipStream_t st)
         hipLaunchKernelGGL(k_gate_h<float>, dim3(g), dim3(256), 0, st, (float2 *)psi, n, q);
     else
         hipLaunchKernelGGL(k_gate_h<double>, dim3(g), dim3(256), 0, st, (double2 *)psi, n, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate_cz(int dtype, void *psi, int n, int a, int b, hipStream_t st)
+{
+    if (a == b || a < 0 || b < 0 || a >= n || b >= n) return hipErrorInvalidValue;
+    const unsigned g = grid_for(1ull << n, 256, 16384);
+    const uint64_t both = (1ull << a) | (1ull << b);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_gate_cz<float>, dim3(g), dim3(256), 0, st, (float2 *)psi, n, both);
+    else
+        hipLaunchKernelGGL(k_gate_cz<double>, dim3(g), dim3(256), 0, st, (double2 *)psi, n, both);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_scale(int dtype, void *psi, int n, uint64_t zero_mask, double scale,
+                                hipStream_t st)
+{
+    const unsigned g = grid_for(1ull << n, 256, 16384);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_project_scale<float>, dim3(g), dim3(256), 0, st, (float2 *)psi, n,
+                           zero_mask, (float)scale);
+    else
+        hipLaunchKernelGGL(k_project_scale<double>, dim3(g), dim3(256), 0, st, (double2 *)psi, n,
+                           zero_mask, scale);
     return hipGetLastError();
 }
 

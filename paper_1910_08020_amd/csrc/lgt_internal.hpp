@@ -128,7 +128,8 @@ std::string describe_plan(const PassPlan &p, int n_links);
 // ---------------------------------------------------------------------------
 enum KernelFamily {
     KF_INIT = 0, KF_LOW, KF_HIGH, KF_PHASE, KF_SMALL, KF_GATE_RX, KF_GATE_RZ, KF_GATE_CNOT,
-    KF_RED_DIAG, KF_RED_FLIP, KF_RED_DOS, KF_SAMPLE, KF_TILE_LOW, KF_TILE_HIGH, KF_GATE_H, KF_COUNT
+    KF_RED_DIAG, KF_RED_FLIP, KF_RED_DOS, KF_SAMPLE, KF_TILE_LOW, KF_TILE_HIGH, KF_GATE_H,
+    KF_GATE_CZ, KF_PROJECT, KF_COUNT
 };
 const char *kernel_family_name(int kf);
 
@@ -200,6 +201,10 @@ hipError_t launch_sum_cols(const double *partials, int rows, int width, int ncol
 hipError_t launch_reduce_popcount(int dtype, const void *psi, int n, const uint32_t *ptab_dev,
                                   double *partials, hipStream_t st);
 hipError_t launch_gate_h(int dtype, void *psi, int n, int q, hipStream_t st);
+hipError_t launch_gate_cz(int dtype, void *psi, int n, int a, int b, hipStream_t st);
+// amplitudes with a bit of zero_mask set become 0, the others are multiplied by scale
+hipError_t launch_project_scale(int dtype, void *psi, int n, uint64_t zero_mask, double scale,
+                                hipStream_t st);
 // psi <- X^xmask Z^zmask psi (Pauli string: Z on the zmask links, then X on the xmask links)
 hipError_t launch_pauli(int dtype, void *psi, int n, uint64_t xmask, uint64_t zmask, hipStream_t st);
 hipError_t launch_reduce_dos(int dtype, const void *psi, int n, const uint32_t *ptab_dev,

@@ -17,8 +17,9 @@ LIB_PATH = os.path.join(_HERE, "liblgt.so")
 LGT_OK, LGT_E_INVALID, LGT_E_UNSUPPORTED, LGT_E_OOM, LGT_E_DEVICE, LGT_E_STATE, LGT_E_BUSY = range(7)
 LGT_C64, LGT_C128 = 0, 1
 LGT_ORDER_TROTTER, LGT_ORDER_SYMMETRIC = 1, 2
-LGT_FORM_FUSED, LGT_FORM_CIRCUIT = 0, 1
-LGT_INIT_PLUS, LGT_INIT_ZGROUND, LGT_INIT_BASIS = 0, 1, 2
+LGT_FORM_FUSED, LGT_FORM_CIRCUIT, LGT_FORM_ANCILLA, LGT_FORM_CONTROLLED = 0, 1, 2, 3
+LGT_INIT_PLUS, LGT_INIT_ZGROUND, LGT_INIT_BASIS, LGT_INIT_ZGROUND_CIRCUIT = 0, 1, 2, 3
+LGT_GATE_H, LGT_GATE_X, LGT_GATE_RX, LGT_GATE_RZ, LGT_GATE_CNOT, LGT_GATE_CZ = range(6)
 LGT_RAMP_PLAQ, LGT_RAMP_COUPLING, LGT_RAMP_EXPLICIT = 0, 1, 2
 LGT_PLAN_NO_MERGE = 8
 (LGT_OBS_NORM, LGT_OBS_Z, LGT_OBS_X, LGT_OBS_PLAQ, LGT_OBS_STAR, LGT_OBS_SIGMAX, LGT_OBS_SIGMAZ,
@@ -44,7 +45,8 @@ class lgt_info_t(ctypes.Structure):
                 ("plaq_masks", ctypes.POINTER(ctypes.c_uint64)),
                 ("plaq_links", ctypes.POINTER(ctypes.c_int32)),
                 ("star_masks", ctypes.POINTER(ctypes.c_uint64)),
-                ("link_plaqs", ctypes.POINTER(ctypes.c_uint32))]
+                ("link_plaqs", ctypes.POINTER(ctypes.c_uint32)),
+                ("n_qubits", ctypes.c_int)]
 
 
 class lgt_observable(ctypes.Structure):
@@ -90,6 +92,8 @@ _SIGNATURES = [
     ("lgt_set_plan", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lgt_thooft_mask", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
     ("lgt_apply_pauli", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_uint64]),
+    ("lgt_apply_gate", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]),
+    ("lgt_create_ancilla", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)]),
     ("lgt_critical_point", ctypes.c_int, [_dp, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp]),
     ("lgt_crossing", ctypes.c_int, [_dp, _dp, _dp, ctypes.c_int, _dp]),
     ("lgt_scan", ctypes.c_int, [_VP, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
@@ -148,6 +152,12 @@ def lgt_create(d, L, periodic=1, dtype=LGT_C64):
     return h
 
 
+def lgt_create_ancilla(d, L, periodic=1, dtype=LGT_C64):
+    h = _VP()
+    _check(lib().lgt_create_ancilla(d, _ints(L), periodic, dtype, ctypes.byref(h)))
+    return h
+
+
 def lgt_create_ex(d, L, periodic, dtype, dev_buf: int, nbytes: int, stream: int | None):
     h = _VP()
     _check(lib().lgt_create_ex(d, _ints(L), periodic, dtype, _VP(dev_buf), nbytes,
@@ -163,7 +173,8 @@ def lgt_info(ctx) -> dict:
     i = lgt_info_t()
     _check(lib().lgt_info(ctx, ctypes.byref(i)), ctx)
     return {
-        "d": i.d, "L": list(i.L)[: i.d], "n_links": i.n_links, "n_plaq": i.n_plaq,
+        "d": i.d, "L": list(i.L)[: i.d], "n_links": i.n_links, "n_qubits": i.n_qubits,
+        "n_plaq": i.n_plaq,
         "n_sites": i.n_sites, "dtype": i.dtype, "state_bytes": i.state_bytes,
         "state": i.state, "stream": i.stream,
         "plaq_masks": np.array(i.plaq_masks[: i.n_plaq], dtype=np.uint64),
@@ -327,6 +338,10 @@ def lgt_thooft_mask(ctx, mu) -> int:
 
 def lgt_apply_pauli(ctx, xmask=0, zmask=0):
     _check(lib().lgt_apply_pauli(ctx, xmask, zmask), ctx)
+
+
+def lgt_apply_gate(ctx, gate, q0, q1=-1, angle=0.0):
+    _check(lib().lgt_apply_gate(ctx, gate, q0, q1, angle), ctx)
 
 
 def lgt_set_plan(ctx, plan: int):
