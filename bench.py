@@ -248,9 +248,11 @@ def variants(lgt):
     out = {}
 
     def per_step(d, L, dtype, n, form=0, order=2, plan=0):
-        ctx = lgt.lgt_create(d, list(L), 1, dtype)
+        anc = form in (lgt.LGT_FORM_ANCILLA, lgt.LGT_FORM_CONTROLLED)
+        ctx = (lgt.lgt_create_ancilla if anc else lgt.lgt_create)(d, list(L), 1, dtype)
         try:
-            lgt.lgt_set_plan(ctx, plan)
+            if not anc:
+                lgt.lgt_set_plan(ctx, plan)
             s = lgt.make_schedule(0.05 * n, n, 1.0, 1.0)
             lgt.lgt_evolve(ctx, s, order, form, 0, min(n, 2))
             lgt.lgt_sync(ctx)
@@ -273,6 +275,10 @@ def variants(lgt):
     out["2x2x2_c128_fused"] = per_step(3, (2, 2, 2), lgt.LGT_C128, 200)
     out["2x2x2_c64_circuit"] = per_step(3, (2, 2, 2), lgt.LGT_C64, 4, form=1)
     out["2x2x2_c128_circuit"] = per_step(3, (2, 2, 2), lgt.LGT_C128, 2, form=1)
+    # eq. (ara) with the ancilla (25 qubits), and its time-direction-controlled variant
+    out["2x2x2_c64_ancilla_25q"] = per_step(3, (2, 2, 2), lgt.LGT_C64, 2, form=lgt.LGT_FORM_ANCILLA)
+    out["2x2x2_c64_controlled_25q"] = per_step(3, (2, 2, 2), lgt.LGT_C64, 2,
+                                               form=lgt.LGT_FORM_CONTROLLED)
     out["4x4_c64_fused_32links"] = per_step(2, (4, 4), lgt.LGT_C64, 8)
     out["4x4_c128_fused_32links"] = per_step(2, (4, 4), lgt.LGT_C128, 4)
     out["3x3_c64_fused_single"] = per_step(2, (3, 3), lgt.LGT_C64, 2000)
@@ -292,6 +298,30 @@ def variants(lgt):
     finally:
         lgt.lgt_destroy(ctx)
     return out
+
+
+def phase_estimation(lgt):
+    """The controlled evolution of the phase-estimation passage on 2x2x2 + ancilla
+    (25 qubits): at g = 0 from (|0> + |1>)/sqrt 2 times the Z ground state, <sigma^x_a>
+    must be cos(2 E t) with E = -N_p."""
+    n, T = 8, 0.2
+    ctx = lgt.lgt_create_ancilla(3, [2, 2, 2], 1, lgt.LGT_C64)
+    try:
+        info = lgt.lgt_info(ctx)
+        N, n_plaq = info["n_links"], info["n_plaq"]
+        lgt.lgt_reset(ctx, lgt.LGT_INIT_ZGROUND_CIRCUIT)
+        lgt.lgt_apply_gate(ctx, lgt.LGT_GATE_H, N)
+        s = lgt.make_schedule(T, n, cx=np.zeros(n), cz=np.ones(n), ramp=lgt.LGT_RAMP_EXPLICIT)
+        t0 = time.perf_counter()
+        lgt.lgt_evolve(ctx, s, lgt.LGT_ORDER_SYMMETRIC, lgt.LGT_FORM_CONTROLLED)
+        sx = lgt.lgt_measure(ctx, lgt.LGT_OBS_X, masks=[1 << N])[0]
+        el = time.perf_counter() - t0
+    finally:
+        lgt.lgt_destroy(ctx)
+    return {"workload": "2x2x2 + ancilla (25 qubits), Z ground state by the projection circuit, "
+                        f"{n} controlled symmetric steps, T={T}, g=0, complex64",
+            "sigma_x_ancilla": float(sx), "expected_cos_2Et": float(np.cos(2 * n_plaq * T)),
+            "seconds": el}
 
 
 def precision(lgt):
@@ -418,6 +448,7 @@ def main():
         line["serving"] = serving(lgt, args.serve_requests, args.serve_rate)
         line["variants"] = variants(lgt)
         line["paper_scans"] = paper_scans(lgt)
+        line["phase_estimation"] = phase_estimation(lgt)
         line["precision"] = precision(lgt)
     print(json.dumps(line), flush=True)
 
