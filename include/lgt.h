@@ -249,7 +249,10 @@ typedef struct {
  * lgt_measure: expectation values normalised by <psi|psi> (except
  * LGT_OBS_NORM), accumulated in FP64 on the GPU, written to the host array
  * out of out_len doubles.  out_len smaller than the result gives
- * LGT_E_INVALID and writes nothing.
+ * LGT_E_INVALID and writes nothing.  Masks of LGT_OBS_Z / LGT_OBS_X may name
+ * any qubit of the context (bit N_l is the ancilla of an ancilla context);
+ * other bits give LGT_E_INVALID.  On an ancilla context the lattice
+ * observables sum over both ancilla values.
  */
 lgt_status lgt_measure(lgt_ctx *ctx, const lgt_observable *obs, double *out, size_t out_len);
 
@@ -258,7 +261,8 @@ lgt_status lgt_measure(lgt_ctx *ctx, const lgt_observable *obs, double *out, siz
  * followed by sigma^x over the xmask links (Sec. 3.5: Wegner-Wilson operators W_mu on
  * non-contractible loops move the initial state between topological sectors; 't Hooft
  * operators V_mu are the sigma^x strings).  In place on the device, stream-ordered.
- * E_INVALID for masks with bits at or beyond N_l.
+ * E_INVALID for masks with bits at or beyond the context's qubit count (N_l, or N_l + 1
+ * with an ancilla).
  */
 lgt_status lgt_apply_pauli(lgt_ctx *ctx, uint64_t xmask, uint64_t zmask);
 
@@ -317,7 +321,8 @@ lgt_status lgt_crossing(const double *g, const double *a, const double *b, int n
 
 /*
  * lgt_sample: n_shots computational-basis samples written to the host array
- * out (bit q of out[i] = link q).  Shot i draws u_i from the counter-based
+ * out (bit q of out[i] = link q; bit N_l the ancilla of an ancilla context).  Shot i
+ * draws u_i from the counter-based
  * SplitMix64 stream (finaliser of seed + (i+1)*0x9E3779B97F4A7C15, top 53
  * bits / 2^53) and returns the smallest b whose FP64 cumulative probability
  * in ascending b exceeds u_i <psi|psi>.  1 <= n_shots <= 2^26.
