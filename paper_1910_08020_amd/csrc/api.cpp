@@ -895,7 +895,7 @@ static lgt_status reduce_masks(lgt_ctx *c, bool flip, const uint64_t *masks, int
 {
     const int n = nq(c);
     const int chunk = flip ? kFlipChunk : kMaskChunk;
-    const int g = reduce_blocks(n);
+    const int g = flip ? reduce_blocks(n) : reduce_diag_blocks(n);
     out.assign(n_masks, 0.0L);
     for (int k0 = 0; k0 < n_masks; k0 += chunk) {
         const int m = std::min(chunk, n_masks - k0);
@@ -1101,7 +1101,7 @@ lgt_status lgt_scan(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, int6
     if (hipMemcpy(mdev, mk.data(), sizeof(uint64_t) * ncol, hipMemcpyHostToDevice) != hipSuccess)
         return bail(LGT_E_DEVICE, "scan mask upload");
     const uint64_t *md = (const uint64_t *)mdev;
-    const int g = reduce_blocks(n);
+    const int g = reduce_blocks(n), gd = reduce_diag_blocks(n);
     std::vector<double> cxs(n_points), czs(n_points);
     for (int64_t k = 0; k < n_points; ++k) {
         double dt = 0;
@@ -1121,7 +1121,7 @@ lgt_status lgt_scan(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, int6
             e = timed(c, KF_RED_DIAG, [&] {
                 return launch_reduce_diag(c->dtype, c->state, n, md + off, m, c->partials, c->stream);
             });
-            if (e == hipSuccess) e = launch_sum_cols(c->partials, g, kMaskChunk, m, row + off, c->stream);
+            if (e == hipSuccess) e = launch_sum_cols(c->partials, gd, kMaskChunk, m, row + off, c->stream);
         }
         for (int off = nd; off < ncol && e == hipSuccess; off += kFlipChunk) {
             const int m = std::min(kFlipChunk, ncol - off);

@@ -190,6 +190,7 @@ hipError_t launch_gate_rz(int dtype, void *psi, int n, int q, double phi, hipStr
 hipError_t launch_gate_cnot(int dtype, void *psi, int n, int c, int t, hipStream_t st);
 // reductions: partial sums per block, FP64
 int reduce_blocks(int n);
+int reduce_diag_blocks(int n);   // partial rows written by launch_reduce_diag
 hipError_t launch_reduce_diag(int dtype, const void *psi, int n, const uint64_t *masks_dev,
                               int n_masks, double *partials, hipStream_t st);
 hipError_t launch_reduce_flip(int dtype, const void *psi, int n, const uint64_t *masks_dev,

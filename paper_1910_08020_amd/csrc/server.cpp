@@ -120,7 +120,7 @@ hipError_t reduce(lgt_server *s, int dtype, const void *psi, int n, bool flip,
                   const uint64_t *masks, int n_masks, std::vector<long double> &out)
 {
     const int chunk = flip ? 8 : 32;
-    const int g = reduce_blocks(n);
+    const int g = flip ? reduce_blocks(n) : reduce_diag_blocks(n);
     out.assign(n_masks, 0.0L);
     for (int k0 = 0; k0 < n_masks; k0 += chunk) {
         const int m = std::min(chunk, n_masks - k0);
