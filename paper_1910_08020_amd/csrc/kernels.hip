@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kLowThreads) void k_low(const DevInst *__restrict__
     __syncthreads();
 
     C v[16];
-    // round 1: registers hold tile bits 8..11, coalesced loads
+    // stage 1: registers hold tile bits 8..11, coalesced loads
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = ldg(psi + (base + t + (r << 8)));
     if (pre >= 0) {
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kLowThreads) void k_low(const DevInst *__restrict__
 #pragma unroll
     for (int r = 0; r < 16; ++r) buf[swz(t + (r << 8))] = v[r];
     __syncthreads();
-    // round 2: registers hold tile bits 4..7
+    // stage 2: registers hold tile bits 4..7
     const int i2 = (t & 15) | ((t >> 4) << 8);
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = buf[swz(i2 | (r << 4))];
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kLowThreads) void k_low(const DevInst *__restrict__
 #pragma unroll
     for (int r = 0; r < 16; ++r) buf[swz(i2 | (r << 4))] = v[r];
     __syncthreads();
-    // round 3: registers hold tile bits 0..3
+    // stage 3: registers hold tile bits 0..3
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = buf[swz(r | (t << 4))];
     rot_regs<T, C, 4>(v, rp.u, rp.v);
