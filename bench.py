@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -39,9 +40,14 @@ def _lgt():
 
 
 def kernel_source_hash() -> str:
-    # the device code only: host-side changes do not invalidate counter readings
-    with open(os.path.join(ROOT, "paper_1910_08020_amd", "csrc", "kernels.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the kernel source with comments and blank space removed: counter readings
+    stay valid across edits of comments and of the other (host) sources."""
+    with open(os.path.join(ROOT, "paper_1910_08020_amd", "csrc", "kernels.hip")) as fh:
+        src = fh.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = " ".join(src.split())
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def run_job(lgt, ctx, w, masks, stars_n, plaq_n):
