@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -10,6 +11,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "lgt_internal.hpp"
@@ -231,6 +233,26 @@ const void *ph_ptr(const Tables &tb, int dtype)
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// f(0) .. f(n-1) on up to 16 host threads (independent items, any order)
+template <typename F>
+void parallel_for(int n, F &&f)
+{
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = std::min(n, (int)std::min(16u, hw));
+    if (nt <= 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::thread> pool;
+    pool.reserve(nt);
+    for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&] {
+            for (int i; (i = next.fetch_add(1)) < n;) f(i);
+        });
+    for (auto &th : pool) th.join();
+}
 
 }  // namespace
 
@@ -1438,18 +1460,23 @@ lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule
     lgt_status s = check_ctx(c0);
     if (s) return fail(nullptr, s, c0->err);
     if (count == 0) return LGT_OK;
-    // every instance's tables in one staging block
+    // every instance's tables in one staging block, built on several host threads (the
+    // FP32 rounding of a 2000-step table takes milliseconds per instance)
     std::vector<Tables> tbs(n_inst);
-    StepTables st;
-    std::vector<uint8_t> forms;
-    for (int i = 0; i < n_inst; ++i) {
+    std::vector<StepTables> sts(n_inst);
+    std::vector<std::string> whys(n_inst);
+    parallel_for(n_inst, [&](int i) {
         double dt;
         std::vector<double> cx, cz;
-        std::string why = schedule_coeffs(&scheds[i], first_step, count, dt, cx, cz);
-        if (!why.empty()) return fail(nullptr, LGT_E_INVALID, why);
-        make_tables(c0->lat, c0->dtype, dt, cx, cz, orders[i], st, tbs[i]);
-        or_forms(st, forms);
+        whys[i] = schedule_coeffs(&scheds[i], first_step, count, dt, cx, cz);
+        if (whys[i].empty()) make_tables(c0->lat, c0->dtype, dt, cx, cz, orders[i], sts[i], tbs[i]);
+    });
+    std::vector<uint8_t> forms;
+    for (int i = 0; i < n_inst; ++i) {
+        if (!whys[i].empty()) return fail(nullptr, LGT_E_INVALID, whys[i]);
+        or_forms(sts[i], forms);
     }
+    const StepTables &st = sts[0];
     const size_t rb = align256(tbs[0].rot_bytes), pb = align256(tbs[0].ph_bytes);
     const size_t ib = align256(sizeof(DevInst) * n_inst);
     const size_t total = (rb + pb) * n_inst + ib;

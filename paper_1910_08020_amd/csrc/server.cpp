@@ -66,7 +66,41 @@ struct Run {
     int n_total = 0, pre = 0, step = 0;
     std::vector<uint8_t> forms;   // per step: 1 tan-form, 2 cot-form link rotation
     double cx_last = 0, cz_last = 0;
+    std::vector<char> blob;        // host copy of the tables, built on the submitting thread
 };
+
+// the run's rot | phase tables (rounded for its dtype), built when it is submitted so that
+// the worker thread only uploads them
+void build_tables(const Lattice &lat, int dtype, Run *r, const std::vector<double> &cx,
+                  const std::vector<double> &cz, double dt)
+{
+    const int n = lat.n_links;
+    r->cx_last = cx.back();
+    r->cz_last = cz.back();
+    StepTables st;
+    build_step_tables(n, lat.n_plaq, dt, cx.data(), cz.data(), (int)cx.size(), r->order, st);
+    auto pack = [&](const auto &rot, const auto &ph) {
+        r->rot_bytes = (rot.size() * sizeof(rot[0]) + 255) & ~(size_t)255;
+        r->blob.resize(r->rot_bytes + ph.size() * sizeof(ph[0]));
+        std::memcpy(r->blob.data(), rot.data(), rot.size() * sizeof(rot[0]));
+        std::memcpy(r->blob.data() + r->rot_bytes, ph.data(), ph.size() * sizeof(ph[0]));
+    };
+    if (dtype == LGT_C64) {
+        std::vector<RotParam<float>> rot;
+        std::vector<Cplx<float>> ph;
+        round_tables_f32(st, n, lat.n_plaq, rot, ph);
+        pack(rot, ph);
+    } else {
+        std::vector<RotParam<double>> rot;
+        std::vector<Cplx<double>> ph;
+        round_tables_f64(st, lat.n_plaq, rot, ph);
+        pack(rot, ph);
+    }
+    r->n_total = st.n_steps;
+    r->pre = st.pre_phase;
+    r->forms.resize(st.n_steps);
+    for (int j = 0; j < st.n_steps; ++j) r->forms[j] = (st.rot_u[j] == 1.0) ? 1 : 2;
+}
 
 }  // namespace
 
@@ -197,35 +231,7 @@ lgt_status admit(lgt_server *s, Run *r)
     const ShapeRes &sr = *r->sr;
     const Lattice &lat = sr.lat;
     const int n = lat.n_links, dtype = r->shape.dtype;
-    double dt;
-    std::vector<double> cx, cz;
-    if (!schedule_coeffs(&r->sched, 0, r->sched.n_steps, dt, cx, cz).empty()) return LGT_E_INVALID;
-    r->cx_last = cx.back();
-    r->cz_last = cz.back();
-    StepTables st;
-    build_step_tables(n, lat.n_plaq, dt, cx.data(), cz.data(), (int)cx.size(), r->order, st);
-    std::vector<char> blob;
-    if (dtype == LGT_C64) {
-        std::vector<RotParam<float>> rot;
-        std::vector<Cplx<float>> ph;
-        round_tables_f32(st, n, lat.n_plaq, rot, ph);
-        r->rot_bytes = (rot.size() * sizeof(rot[0]) + 255) & ~(size_t)255;
-        blob.resize(r->rot_bytes + ph.size() * sizeof(ph[0]));
-        std::memcpy(blob.data(), rot.data(), rot.size() * sizeof(rot[0]));
-        std::memcpy(blob.data() + r->rot_bytes, ph.data(), ph.size() * sizeof(ph[0]));
-    } else {
-        std::vector<RotParam<double>> rot;
-        std::vector<Cplx<double>> ph;
-        round_tables_f64(st, lat.n_plaq, rot, ph);
-        r->rot_bytes = (rot.size() * sizeof(rot[0]) + 255) & ~(size_t)255;
-        blob.resize(r->rot_bytes + ph.size() * sizeof(ph[0]));
-        std::memcpy(blob.data(), rot.data(), rot.size() * sizeof(rot[0]));
-        std::memcpy(blob.data() + r->rot_bytes, ph.data(), ph.size() * sizeof(ph[0]));
-    }
-    r->n_total = st.n_steps;
-    r->pre = st.pre_phase;
-    r->forms.resize(st.n_steps);
-    for (int j = 0; j < st.n_steps; ++j) r->forms[j] = (st.rot_u[j] == 1.0) ? 1 : 2;
+    const std::vector<char> &blob = r->blob;
     r->step = 0;
     if (hipMallocAsync(&r->psi, sr.state_bytes, s->stream) != hipSuccess) return LGT_E_OOM;
     if (hipMallocAsync(&r->tables, blob.size() + 256, s->stream) != hipSuccess) return LGT_E_OOM;
@@ -417,6 +423,7 @@ lgt_status lgt_server_submit(lgt_server *s, const lgt_request *req, uint64_t *ti
     sh.dtype = req->dtype;
     for (int i = 0; i < 3; ++i) sh.L[i] = (i < req->d) ? req->L[i] : 1;
     Run *r = new Run();
+    r->t_submit = Clock::now();
     r->shape = sh;
     r->sched = req->sched;
     r->order = req->order;
@@ -465,8 +472,12 @@ lgt_status lgt_server_submit(lgt_server *s, const lgt_request *req, uint64_t *ti
         delete r;
         return LGT_E_OOM;
     }
+    // the tables are built here, on the caller's thread, outside the lock (the shape's
+    // lattice stays put in the map)
+    lk.unlock();
+    build_tables(sr.lat, sh.dtype, r, cx, cz, dt);
+    lk.lock();
     r->ticket = s->next_ticket++;
-    r->t_submit = Clock::now();
     *ticket = r->ticket;
     s->results[r->ticket] = lgt_result{};
     s->pending.push_back(r);
