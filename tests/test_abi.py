@@ -35,6 +35,28 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name)
 
 
+def test_header_and_library_from_plain_c(tmp_path):
+    """The boundary is plain C: the header compiles as C99 with -pedantic, and a C program
+    linked against the library queries a lattice (host-only call, no GPU work)."""
+    src = tmp_path / "q.c"
+    src.write_text(
+        '#include <stdio.h>\n#include "lgt.h"\n'
+        "int main(void) {\n"
+        "    int L[3] = {2, 2, 2}, nl = 0, np = 0, ns = 0;\n"
+        "    if (lgt_lattice_query(3, L, &nl, &np, &ns, NULL, NULL) != LGT_OK) return 1;\n"
+        "    int bad[2] = {1, 4};\n"
+        "    if (lgt_lattice_query(2, bad, &nl, NULL, NULL, NULL, NULL) != LGT_E_INVALID) return 2;\n"
+        '    printf("%d %d %d\\n", nl, np, ns);\n'
+        "    return 0;\n}\n")
+    exe = tmp_path / "q"
+    libdir = os.path.dirname(lgt.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    "-I", os.path.dirname(HEADER), str(src), "-o", str(exe), "-L", libdir,
+                    "-l:liblgt.so", f"-Wl,-rpath,{libdir}"], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    assert out.split() == ["24", "24", "8"]
+
+
 def test_binding_covers_every_symbol():
     bound = {s[0] for s in lgt._SIGNATURES}
     assert set(_declared()) == bound
