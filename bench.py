@@ -249,6 +249,41 @@ def paper_scans(lgt):
     return out
 
 
+def bandwidth_sweep(lgt, steps=50, reps=5):
+    """Complex64 tori from 24 to 32 links, symmetric steps: median time per Trotter step over
+    `reps` calls of `steps` steps, the bytes the plan moves (one read and one write of the
+    state per launch) and the algorithmic two passes' worth, each against 8 TB/s."""
+    out = {}
+    for d, L in ((2, (3, 4)), (3, (2, 2, 2)), (2, (2, 7)), (2, (3, 5)), (2, (4, 4))):
+        ctx = lgt.lgt_create(d, list(L), 1, lgt.LGT_C64)
+        try:
+            info = lgt.lgt_info(ctx)
+            sb = info["state_bytes"]
+            desc = lgt.lgt_plan_describe(ctx)
+            n_pass = desc.split(";")[0].count("|") + 1
+            merged = "steps merged" in desc
+            launches = steps * (n_pass - 1) + 1 if merged else steps * n_pass
+            s = lgt.make_schedule(0.05 * steps, steps, 1.0, 1.0)
+            lgt.lgt_evolve(ctx, s, lgt.LGT_ORDER_SYMMETRIC, lgt.LGT_FORM_FUSED, 0, 4)
+            lgt.lgt_sync(ctx)
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                lgt.lgt_evolve(ctx, s, lgt.LGT_ORDER_SYMMETRIC, lgt.LGT_FORM_FUSED, 0, steps)
+                lgt.lgt_sync(ctx)
+                ts.append(time.perf_counter() - t0)
+            t = float(np.median(ts)) / steps
+        finally:
+            lgt.lgt_destroy(ctx)
+        moved = launches / steps * 2 * sb
+        out["x".join(map(str, L))] = {
+            "links": info["n_links"], "plan": desc, "launches_per_step": launches / steps,
+            "us_per_step": t * 1e6, "implementation_GBps": moved / t / 1e9,
+            "implementation_hbm_frac": moved / t / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_hbm_frac": 2 * sb / t / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
 def variants(lgt):
     """Per-Trotter-step time of the other precisions, forms and sizes (secondary)."""
     out = {}
@@ -453,6 +488,7 @@ def main():
         line["lambda_scan"] = lambda_scan(lgt)
         line["serving"] = serving(lgt, args.serve_requests, args.serve_rate)
         line["variants"] = variants(lgt)
+        line["bandwidth_sweep"] = bandwidth_sweep(lgt)
         line["paper_scans"] = paper_scans(lgt)
         line["phase_estimation"] = phase_estimation(lgt)
         line["precision"] = precision(lgt)
