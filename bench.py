@@ -20,6 +20,7 @@ import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -188,7 +189,47 @@ def cpu_baseline(target_s=12.0, max_steps=200):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": upd / el, "unit": "amp-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} symmetric Trotter steps (of 2000) of the 2x2x2 (24-link) run at "
-                      f"lambda={w.lambdas[0]}, complex128 oracle, OpenMP loops, {el:.1f} s"}
+                      f"lambda={w.lambdas[0]}, complex128 oracle, OpenMP loops, {el:.1f} s",
+            "single_thread": _oracle_single_thread(),
+            "host": _host_info()}
+
+
+def _host_info() -> dict:
+    cpu, mem = "", 0.0
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+        with open("/proc/meminfo") as fh:
+            kb = next((int(ln.split()[1]) for ln in fh if ln.startswith("MemTotal")), 0)
+        mem = kb / 2**20
+    except OSError:
+        pass
+    return {"cpu": cpu, "logical_cpus": os.cpu_count(), "ram_gib": round(mem, 1)}
+
+
+def _oracle_single_thread(target_s=4.0) -> dict | None:
+    """The same oracle steps with one OpenMP thread, in a child process (the thread count is
+    fixed when the oracle library loads)."""
+    code = (
+        "import sys, time, json; sys.path.insert(0, %r)\n"
+        "import oracle, workloads\n"
+        "lat = oracle.Lattice(3, (2, 2, 2)); w = workloads.CONFIG3\n"
+        "dt, cx, cz = oracle.schedule_plaquette_ramp(w.T, w.n_steps, w.lambdas[0], 1.0)\n"
+        "psi = oracle.plus_state(lat.N); done = 0; el = 0.0\n"
+        "while el < %r and done < 50:\n"
+        "    t0 = time.perf_counter()\n"
+        "    oracle.evolve(psi, lat, dt, cx[done:done + 1], cz[done:done + 1], w.order)\n"
+        "    el += time.perf_counter() - t0; done += 1\n"
+        "print(json.dumps([done, el]))\n") % (ROOT, target_s)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                           timeout=120)
+        done, el = json.loads(r.stdout.strip().splitlines()[-1])
+    except Exception:
+        return None
+    return {"value": done * (1 << 24) * 25 / el, "unit": "amp-updates/s", "cores": 1,
+            "sample": f"{done} symmetric Trotter steps of the same run, {el:.1f} s"}
 
 
 def paper_scans(lgt):
