@@ -528,6 +528,8 @@ def main():
     if not args.no_extras:
         line["lambda_scan"] = lambda_scan(lgt)
         line["serving"] = serving(lgt, args.serve_requests, args.serve_rate)
+        # offered load below, near and above the mix's service rate (about 20 solves/s)
+        line["serving_load_sweep"] = [serving(lgt, int(4 * r), r) for r in (10.0, 20.0, 40.0)]
         line["variants"] = variants(lgt)
         line["bandwidth_sweep"] = bandwidth_sweep(lgt)
         line["paper_scans"] = paper_scans(lgt)
