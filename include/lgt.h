@@ -169,7 +169,9 @@ lgt_status lgt_line_mask(const lgt_ctx *ctx, int site, int mu, uint64_t *mask);
  */
 lgt_status lgt_thooft_mask(const lgt_ctx *ctx, int mu, uint64_t *mask);
 
-/* lgt_reset: overwrite the state (Sec. 2.3). basis_index < 2^N for LGT_INIT_BASIS. */
+/* lgt_reset: overwrite the state (Sec. 2.3).  basis_index < 2^(number of qubits) for
+ * LGT_INIT_BASIS (N_l, or N_l + 1 with an ancilla); LGT_INIT_ZGROUND_CIRCUIT needs an
+ * ancilla context (LGT_E_UNSUPPORTED otherwise). */
 lgt_status lgt_reset(lgt_ctx *ctx, lgt_init init, uint64_t basis_index);
 
 /* ---------------------------------------------------------------------------
