@@ -460,6 +460,8 @@ def main():
                     help="profiling runs only: Trotter steps per lambda instead of the full "
                          "schedule, plus one device-to-device copy of the state (a copy of "
                          "known size for counter calibration); prints no benchmark line")
+    ap.add_argument("--profile-lattice", default="2x2x2",
+                    help="profiling runs only: the torus, e.g. 2x7 or 4x4 (complex64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs one state per GPU; only --gpus 1 is "
@@ -468,20 +470,23 @@ def main():
     lgt = _lgt()
 
     w = workloads.CONFIG3
-    ctx = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64)
-    info = lgt.lgt_info(ctx)
     if args.profile_steps > 0:
-        other = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64)
+        L = [int(x) for x in args.profile_lattice.split("x")]
+        ctx = lgt.lgt_create(len(L), L, 1, lgt.LGT_C64)
+        info = lgt.lgt_info(ctx)
+        other = lgt.lgt_create(len(L), L, 1, lgt.LGT_C64)
         for lam in w.lambdas[:1]:
             s = lgt.make_schedule(w.T, w.n_steps, lam, 1.0)
             lgt.lgt_evolve(ctx, s, w.order, lgt.LGT_FORM_FUSED, 0, args.profile_steps)
         lgt.lgt_copy_state(other, ctx)
         lgt.lgt_sync(other)
-        print(json.dumps({"profile_steps": args.profile_steps,
+        print(json.dumps({"profile_steps": args.profile_steps, "lattice": args.profile_lattice,
                           "copy_bytes": info["state_bytes"]}), flush=True)
         lgt.lgt_destroy(other)
         lgt.lgt_destroy(ctx)
         return
+    ctx = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64)
+    info = lgt.lgt_info(ctx)
     n_links, n_plaq, n_sites = info["n_links"], info["n_plaq"], info["n_sites"]
     masks = [int(m) for m in info["plaq_masks"][:4]] + [lgt.lgt_line_mask(ctx, 0, mu)
                                                         for mu in range(3)]
