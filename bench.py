@@ -41,10 +41,13 @@ def _lgt():
 
 
 def kernel_source_hash() -> str:
-    """Hash of the kernel source with comments and blank space removed: counter readings
-    stay valid across edits of comments and of the other (host) sources."""
-    with open(os.path.join(ROOT, "paper_1910_08020_amd", "csrc", "kernels.hip")) as fh:
-        src = fh.read()
+    """Hash of the kernel sources (kernels.hip and the tile layouts) with comments and blank
+    space removed: counter readings stay valid across edits of comments and of the host
+    sources."""
+    src = ""
+    for name in ("kernels.hip", "tile_layout.hpp"):
+        with open(os.path.join(ROOT, "paper_1910_08020_amd", "csrc", name)) as fh:
+            src += fh.read()
     src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
     src = re.sub(r"//[^\n]*", " ", src)
     src = " ".join(src.split())
