@@ -1238,11 +1238,12 @@ static hipError_t launch_pass_t(const DevInst *dev_inst, int n_inst, int n, int 
 int pass_wave_bits(int dtype, int low, int h, int cb)
 {
     // low tile of h = 10+W bits, 2 <= W <= 4 (complex64) / 3 (complex128).  High tile with
-    // rows of 2^cb amplitudes rotates (6-cb) lane bits + 4 register bits + W wave bits.
+    // rows of 2^cb amplitudes rotates (6-cb) lane bits + 4 register bits + W wave bits;
+    // rows of 128, 256 or 512 bytes (complex64), 128 or 256 bytes (complex128).
     const int wmax = dtype == LGT_C64 ? 4 : 3;
     if (low) return (h - 10 >= 2 && h - 10 <= wmax) ? h - 10 : -1;
-    const int cb_lo = dtype == LGT_C64 ? 4 : 3;
-    if (cb < cb_lo || cb > cb_lo + 1) return -1;
+    const int cb_lo = dtype == LGT_C64 ? 4 : 3, cb_hi = dtype == LGT_C64 ? 6 : 4;
+    if (cb < cb_lo || cb > cb_hi) return -1;
     const int w = h - (10 - cb);
     return (w < 0 || w > wmax) ? -1 : w;
 }
@@ -1281,6 +1282,10 @@ hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, in
         if (cb == 4) {
             LGT_PASS_CASES(float, 4)
             return launch_pass_t<float, 4, 4>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st);
+        }
+        if (cb == 6) {
+            LGT_PASS_CASES(float, 6)
+            return launch_pass_t<float, 4, 6>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st);
         }
         LGT_PASS_CASES(float, 5)
         return launch_pass_t<float, 4, 5>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st);
