@@ -406,6 +406,21 @@ const char *lgt_last_error(const lgt_ctx *ctx);
 lgt_status lgt_batch_evolve(int n, lgt_ctx *const *ctxs, const lgt_schedule *scheds,
                             const lgt_order *orders, int64_t first_step, int64_t count);
 
+/*
+ * lgt_set_graphs: on != 0 makes lgt_batch_evolve calls whose first context is ctx capture
+ * their launch sequence into a HIP graph once per structure (instances, step count, plan,
+ * rotation forms, table layout) and replay it on later calls with the same structure;
+ * the tables are uploaded before each replay, outside the graph, and the graph holds
+ * kernel launches only.  Results are bit for bit those of direct launches.  While
+ * profiling is on, and on a context that runs on the null stream, batches launch
+ * directly.  At most 64 graphs are kept per context; the cache is dropped whole when full.
+ * Measured on MI355X the replay takes as long
+ * as direct launches (the gap between dependent kernels is on the device), so it is off
+ * by default; it serves callers that want one host call per batch.  on = 0 also frees the
+ * cached graphs.
+ */
+lgt_status lgt_set_graphs(lgt_ctx *ctx, int on);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of adiabatic runs of mixed lattice sizes
  * ------------------------------------------------------------------------- */

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -62,6 +63,9 @@ struct lgt_ctx {
     double prof_ms[KF_COUNT] = {0};
     int plan = 0;   // pass plan code (plan_passes), 0 = built-in rule
     int n_anc = 0;  // 1: one ancilla qubit on bit N_l above the links
+    // captured launch sequences of batched evolutions, by structure (lgt_set_graphs)
+    bool use_graphs = false;
+    std::map<std::string, hipGraphExec_t> graphs;
     std::string err;
 };
 
@@ -429,6 +433,9 @@ hipError_t enqueue_fused_range(int dtype, int n, int n_plaq, const DevInst *dev_
 
 }  // namespace lgt
 
+// graphs kept per context for batched evolutions
+static constexpr size_t kMaxGraphs = 64;
+
 static hipError_t enqueue_fused(lgt_ctx *c, const DevInst *dev_inst, int n_inst, int count,
                                 int pre_phase, const uint8_t *forms)
 {
@@ -541,6 +548,7 @@ lgt_status lgt_destroy(lgt_ctx *c)
         (void)hipEventDestroy(pe.b);
     }
     for (auto ev : c->pool) (void)hipEventDestroy(ev);
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
     if (c->own_state && c->state) (void)hipFree(c->state);
     if (c->ptab_dev) (void)hipFree(c->ptab_dev);
     if (c->rot_dev) (void)hipFree(c->rot_dev);
@@ -1305,6 +1313,19 @@ lgt_status lgt_sync(lgt_ctx *c)
     return LGT_OK;
 }
 
+lgt_status lgt_set_graphs(lgt_ctx *c, int on)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (!on) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+        c->graphs.clear();
+    }
+    c->use_graphs = on != 0;
+    return LGT_OK;
+}
+
 lgt_status lgt_set_profiling(lgt_ctx *c, int on)
 {
     lgt_status s = check_ctx(c);
@@ -1507,8 +1528,41 @@ lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule
     if (hipMemcpyAsync(dev, stg, total, hipMemcpyHostToDevice, c0->stream) != hipSuccess ||
         hipEventRecord(c0->stage_free, c0->stream) != hipSuccess)
         return fail(nullptr, LGT_E_DEVICE, "batch upload");
-    hipError_t e = enqueue_fused(c0, (const DevInst *)(dev + (rb + pb) * n_inst), n_inst, (int)count,
-                                 st.pre_phase, forms.data());
+    const DevInst *dinst = (const DevInst *)(dev + (rb + pb) * n_inst);
+    hipError_t e = hipSuccess;
+    // the null stream cannot be captured: batches on it launch directly
+    if (c0->use_graphs && !c0->profiling && c0->stream) {
+        // the launches depend only on this key (the tables and state pointers are read
+        // from the instance array on the device): the same key replays the same graph
+        std::string key = std::to_string(n_inst) + ":" + std::to_string(count) + ":" +
+                          std::to_string(c0->plan) + ":" + std::to_string(st.pre_phase) + ":" +
+                          std::to_string((uintptr_t)dinst) + ":";
+        key.append((const char *)forms.data(), forms.size());
+        auto it = c0->graphs.find(key);
+        if (it == c0->graphs.end() && c0->graphs.size() >= kMaxGraphs) {
+            // a bounded cache: drop every graph once the last launch of one has ended
+            if ((e = hipStreamSynchronize(c0->stream)) != hipSuccess)
+                return fail(nullptr, LGT_E_DEVICE, std::string("batch sync: ") + hipGetErrorString(e));
+            for (auto &g : c0->graphs) (void)hipGraphExecDestroy(g.second);
+            c0->graphs.clear();
+        }
+        if (it == c0->graphs.end()) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            e = hipStreamBeginCapture(c0->stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t el = enqueue_fused(c0, dinst, n_inst, (int)count, st.pre_phase, forms.data());
+                e = hipStreamEndCapture(c0->stream, &graph);
+                if (el != hipSuccess) e = el;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e == hipSuccess) it = c0->graphs.emplace(key, exec).first;
+        }
+        if (e == hipSuccess) e = hipGraphLaunch(it->second, c0->stream);
+    } else {
+        e = enqueue_fused(c0, dinst, n_inst, (int)count, st.pre_phase, forms.data());
+    }
     if (e != hipSuccess) return fail(nullptr, LGT_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     // the other contexts must not race ahead of the shared launches
     for (int i = 1; i < n_inst; ++i)

@@ -93,6 +93,7 @@ _SIGNATURES = [
     ("lgt_thooft_mask", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
     ("lgt_apply_pauli", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_uint64]),
     ("lgt_apply_gate", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]),
+    ("lgt_set_graphs", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lgt_create_ancilla", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)]),
     ("lgt_critical_point", ctypes.c_int, [_dp, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp]),
     ("lgt_crossing", ctypes.c_int, [_dp, _dp, _dp, ctypes.c_int, _dp]),
@@ -342,6 +343,10 @@ def lgt_apply_pauli(ctx, xmask=0, zmask=0):
 
 def lgt_apply_gate(ctx, gate, q0, q1=-1, angle=0.0):
     _check(lib().lgt_apply_gate(ctx, gate, q0, q1, angle), ctx)
+
+
+def lgt_set_graphs(ctx, on: bool):
+    _check(lib().lgt_set_graphs(ctx, 1 if on else 0), ctx)
 
 
 def lgt_set_plan(ctx, plan: int):
