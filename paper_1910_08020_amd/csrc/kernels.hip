@@ -1216,12 +1216,17 @@ static hipError_t launch_pass_t(const DevInst *dev_inst, int n_inst, int n, int 
 {
     constexpr int TB = 10 + W;
     const uint64_t n_tiles = 1ull << (n - TB);
-    // resident workgroups per CU: one for 128 KiB tiles, more for smaller ones; a batch
-    // splits the resident slots of the 256 CUs between its instances
-    const uint64_t per_cu = (W >= 3) ? 1 : (W == 2 ? 2 : 4);
+    // resident workgroups per CU: one for the 512- and 1024-thread tiles, else as many as
+    // the 160 KiB of LDS holds, at most four (with two, batches of 21-64 18-link states ran
+    // 6-7% slower); a batch splits the resident slots of the 256 CUs between its instances,
+    // and each instance's tiles are spread evenly over as few workgroups as take the same
+    // number of rounds
+    constexpr uint64_t tile_bytes = (uint64_t)sizeof(cplx_t<T>) << TB;
+    const uint64_t per_cu = (W >= 3) ? 1 : std::min<uint64_t>(4, (160ull << 10) / tile_bytes);
     uint64_t slots = 256 * per_cu / (uint64_t)n_inst;
     if (slots < 1) slots = 1;
-    const uint64_t grid = n_tiles < slots ? n_tiles : slots;
+    const uint64_t rounds = (n_tiles + slots - 1) / slots;
+    const uint64_t grid = (n_tiles + rounds - 1) / rounds;
     const dim3 g((unsigned)grid, (unsigned)n_inst), b(64 << W);
     if constexpr (PassGeom<T, W, ROWB>::LOW) {
         // Low tiles of states too large to stay in the 256 MB Infinity Cache between passes
