@@ -896,6 +896,7 @@ static lgt_status evolve_fused(lgt_ctx *c, double dt, const std::vector<double> 
     // the single on-chip kernel runs every step at once
     const bool chunked = !small_supported(c->dtype, n);
     FusedCursor cur;
+    PhaseRounding prnd;   // phase-row rounding state carried from chunk to chunk
     for (int j0 = 0, len = kFirstChunk; j0 < total; j0 += len, len *= 2) {
         const int j1 = chunked ? (int)std::min<int64_t>(total, (int64_t)j0 + len) : total;
         // rows read by the launches of steps [j0, j1): link layers j0 .. j1 (a merged launch
@@ -903,7 +904,7 @@ static lgt_status evolve_fused(lgt_ctx *c, double dt, const std::vector<double> 
         // previous chunk already sent link layer j0
         const int r0 = j0 == 0 ? 0 : j0 + 1, r1 = std::min(total, j1 + 1);
         const int k0 = j0 == 0 ? 0 : j0 + pre, k1 = j1 + pre;
-        if (f32) round_phase_f32(st, lat.n_plaq, gain, k0, k1, tb.pf);
+        if (f32) round_phase_f32(st, lat.n_plaq, gain, k0, k1, tb.pf, prnd);
         const char *rsrc = (const char *)rot_ptr(tb, c->dtype), *psrc = (const char *)ph_ptr(tb, c->dtype);
         if (r1 > r0) {
             const size_t off = rot_row * r0, len_b = rot_row * (size_t)(r1 - r0);

@@ -101,6 +101,23 @@ __device__ __forceinline__ C cmul(C a, C b)
     return r;
 }
 
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// a * b for a phase-table entry b.  Over small time steps b.x lies within a few ulps of
+// +-1; a product by such a factor, rounded on its own, moves by a whole ulp or not at all,
+// the same way every step, and the norm of a complex64 state drifted by 1e-8 per step.
+// Here the products with b.x stay inside the FMA and are rounded once together with the
+// b.y terms.
+template <typename C>
+__device__ __forceinline__ C cmul_ph(C a, C b)
+{
+    C r;
+    r.x = fma_r(a.x, b.x, -(a.y * b.y));
+    r.y = fma_r(a.y, b.x, a.x * b.y);
+    return r;
+}
+
 // (a0, a1) <- (u a0 + i v a1, i v a0 + u a1): the link rotation up to the scale
 // folded into the phase table.  One of u, v is exactly 1.
 template <typename T, typename C>
@@ -138,7 +155,7 @@ __device__ __forceinline__ void apply_phase_regs(C *v, uint32_t P0, const uint32
 #pragma unroll
         for (int k = 0; k < B; ++k)
             if (r & (1 << k)) P ^= qs[k];
-        v[r] = cmul(v[r], table[__popc(P)]);
+        v[r] = cmul_ph(v[r], table[__popc(P)]);
     }
 }
 
@@ -148,7 +165,7 @@ template <typename C>
 __device__ __forceinline__ void apply_phase_pr(C *v, uint32_t P0, const uint32_t *pr, const C *table)
 {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], table[__popc(P0 ^ pr[r])]);
+    for (int r = 0; r < 16; ++r) v[r] = cmul_ph(v[r], table[__popc(P0 ^ pr[r])]);
 }
 
 // plaquette sets of the 16 register combinations from the 4 single-bit sets, kept in
@@ -601,7 +618,7 @@ __global__ __launch_bounds__(256) void k_phase(const DevInst *__restrict__ insts
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (r & (1 << k)) P ^= qs[k];
-                stg(psi + (base + r), cmul(ldg(psi + (base + r)), ph[__popc(P)]));
+                stg(psi + (base + r), cmul_ph(ldg(psi + (base + r)), ph[__popc(P)]));
             }
         }
     }
@@ -639,7 +656,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(const DevInst *__restri
     if (pre) {
         for (int i = t; i < np1; i += kSmallThreads) ph[i] = ldg(phase + ((size_t)k * np1 + i));
         __syncthreads();
-        for (int b = t; b < dim; b += kSmallThreads) a[b] = cmul(a[b], ph[syn[b]]);
+        for (int b = t; b < dim; b += kSmallThreads) a[b] = cmul_ph(a[b], ph[syn[b]]);
         ++k;
     }
     __syncthreads();
@@ -655,7 +672,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(const DevInst *__restri
         }
         for (int i = t; i < np1; i += kSmallThreads) ph[i] = ldg(phase + ((size_t)k * np1 + i));
         __syncthreads();
-        for (int b = t; b < dim; b += kSmallThreads) a[b] = cmul(a[b], ph[syn[b]]);
+        for (int b = t; b < dim; b += kSmallThreads) a[b] = cmul_ph(a[b], ph[syn[b]]);
         __syncthreads();
     }
     for (int b = t; b < dim; b += kSmallThreads) stg(psi + b, a[b]);
@@ -724,7 +741,7 @@ __global__ __launch_bounds__(64) void k_wave(const DevInst *__restrict__ insts, 
         if (l < np1) ph[l] = ldg(phase + ((size_t)k * np1 + l));
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = cmul(v[r], ph[m[r]]);
+        for (int r = 0; r < R; ++r) v[r] = cmul_ph(v[r], ph[m[r]]);
         __syncthreads();
     };
     int k = in.ph0;

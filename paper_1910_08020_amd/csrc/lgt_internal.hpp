@@ -68,16 +68,27 @@ struct StepTables {
 void build_step_tables(int n_links, int n_plaq, double dt, const double *cx, const double *cz,
                        int n_steps, int order, StepTables &out);
 
-// Round to complex64 tables; chooses each float (u, v) and phase entry among
-// nearby floats so the norm of one full step stays 1 to FP32 rounding.
+// Round to complex64 tables: the float (u, v) to nearest; the phase rows undo the link
+// layers' norm gains, each gain at its own row once the gains not yet undone reach 2^-12
+// (else at a later row, at the latest the call's last), and each entry is chosen among
+// nearby floats so that its magnitudes multiply to their targets within about one FP32
+// ulp over the whole run (the entry's magnitude error is carried from row to row).
 void round_tables_f32(const StepTables &in, int n_links, int n_plaq,
                       std::vector<RotParam<float>> &rot, std::vector<Cplx<float>> &ph);
+// What the phase rounding carries from row to row: per entry, the magnitude error so far;
+// the link layers' gain not yet undone.
+struct PhaseRounding {
+    std::vector<double> carry;
+    long double gain = 1.0L;
+};
 // The same rounding in pieces: every link layer (with its norm gain), then phase rows
-// [k0, k1) into a table sized for all rows.  Rows come out identical to the whole-table call.
+// [k0, k1) into a table sized for all rows, in increasing order, with one PhaseRounding
+// (fresh at the first row) passed on from piece to piece.  Rows come out identical to the
+// whole-table call.
 void round_rot_f32(const StepTables &in, int n_links, std::vector<RotParam<float>> &rot,
                    std::vector<long double> &gain);
 void round_phase_f32(const StepTables &in, int n_plaq, const std::vector<long double> &gain,
-                     int k0, int k1, std::vector<Cplx<float>> &ph);
+                     int k0, int k1, std::vector<Cplx<float>> &ph, PhaseRounding &pr);
 void round_tables_f64(const StepTables &in, int n_plaq,
                       std::vector<RotParam<double>> &rot, std::vector<Cplx<double>> &ph);
 

@@ -97,9 +97,15 @@ void build_step_tables(int n_links, int n_plaq, double dt, const double *cx, con
     }
 }
 
-// Nearest float, then the +-2 ulp neighbourhood searched for the pair whose
-// squared magnitude is closest to the target (ties: closest to the value).
-static void round_pair_norm(double x, double y, double target2, float &fx, float &fy)
+// Nearest float, then the +-2 ulp neighbourhood searched for the pair whose relative
+// squared-magnitude error, added to `carry` (the error of the same entry summed over the
+// rows before it), is smallest in magnitude (ties: closest to the value).  Returns the
+// chosen pair's error.  Choosing for the running sum rather than for each row alone keeps
+// the product of a run's magnitudes within about one ulp of its target: for slowly varying
+// couplings the nearest magnitude misses its target by the same amount, with the same
+// sign, for thousands of rows, and over 10^6 rows those misses sum to 1e-2.
+static double round_pair_norm(double x, double y, double target2, double carry, float &fx,
+                              float &fy)
 {
     const float x0 = (float)x, y0 = (float)y;
     float cx[5], cy[5];
@@ -111,21 +117,24 @@ static void round_pair_norm(double x, double y, double target2, float &fx, float
     cy[3] = std::nextafter(y0, INFINITY);  cy[4] = std::nextafter(cy[3], INFINITY);
     // a float squared is exact in double (24-bit significands), so a*a + b*b carries one
     // rounding at most: far below the spacing of the candidates' magnitudes (~1e-7)
-    double best = std::numeric_limits<double>::infinity(), bestd = best;
+    double best = std::numeric_limits<double>::infinity(), bestd = best, beste = 0;
     fx = x0;
     fy = y0;
     for (int i = 0; i < 5; ++i)
         for (int k = 0; k < 5; ++k) {
             const double a = cx[i], b = cy[k];
-            const double e = std::fabs(a * a + b * b - target2);
+            const double rel = (a * a + b * b) / target2 - 1.0;
+            const double e = std::fabs(carry + rel);
             const double dd = (a - x) * (a - x) + (b - y) * (b - y);
             if (e < best || (e == best && dd < bestd)) {
                 best = e;
                 bestd = dd;
+                beste = rel;
                 fx = cx[i];
                 fy = cy[k];
             }
         }
+    return beste;
 }
 
 void round_rot_f32(const StepTables &in, int n_links, std::vector<RotParam<float>> &rot,
@@ -142,14 +151,26 @@ void round_rot_f32(const StepTables &in, int n_links, std::vector<RotParam<float
 }
 
 void round_phase_f32(const StepTables &in, int n_plaq, const std::vector<long double> &gain,
-                     int k0, int k1, std::vector<Cplx<float>> &ph)
+                     int k0, int k1, std::vector<Cplx<float>> &ph, PhaseRounding &pr)
 {
+    // Norm gains of the link layers smaller than this are carried to a later phase row:
+    // a phase entry whose magnitude is within a few ulps of 1 is applied as a whole ulp or
+    // not at all (the same way every row), while one at least this far from 1 is applied
+    // to the nearest ulp.  Every call's last row takes what is left, so a call ends with
+    // the norm it started with.
+    constexpr long double kFoldLog = 1.0L / 4096;
     const int np1 = n_plaq + 1;
     if (ph.size() < (size_t)in.n_phase * np1) ph.resize((size_t)in.n_phase * np1);
+    if (pr.carry.size() != (size_t)np1) pr.carry.assign(np1, 0.0);
     for (int k = k0; k < k1; ++k) {
-        // the phase after link layer j undoes that layer's gain exactly
+        // the phase after link layer j undoes that layer's gain, now or at a later row
         const int j = k - in.pre_phase;
-        const long double target2 = (j >= 0) ? 1.0L / gain[j] : 1.0L;
+        if (j >= 0) pr.gain *= gain[j];
+        long double target2 = 1.0L;
+        if (k == in.n_phase - 1 || std::fabs(std::log(pr.gain)) > kFoldLog) {
+            target2 = 1.0L / pr.gain;
+            pr.gain = 1.0L;
+        }
         // sign of the folded cos^N / sin^N factor, from the FP64 table
         double mag = 0;
         for (int m = 0; m < np1; ++m)
@@ -158,8 +179,8 @@ void round_phase_f32(const StepTables &in, int n_plaq, const std::vector<long do
         const double rescale = (mag > 0) ? std::sqrt((double)target2) / mag : 1.0;
         for (int m = 0; m < np1; ++m) {
             const size_t i = (size_t)k * np1 + m;
-            round_pair_norm(in.ph_re[i] * rescale, in.ph_im[i] * rescale, (double)target2,
-                            ph[i].re, ph[i].im);
+            pr.carry[m] += round_pair_norm(in.ph_re[i] * rescale, in.ph_im[i] * rescale,
+                                           (double)target2, pr.carry[m], ph[i].re, ph[i].im);
         }
     }
 }
@@ -170,7 +191,8 @@ void round_tables_f32(const StepTables &in, int n_links, int n_plaq,
     std::vector<long double> gain;
     round_rot_f32(in, n_links, rot, gain);
     ph.assign((size_t)in.n_phase * (n_plaq + 1), Cplx<float>{});
-    round_phase_f32(in, n_plaq, gain, 0, in.n_phase, ph);
+    PhaseRounding pr;
+    round_phase_f32(in, n_plaq, gain, 0, in.n_phase, ph, pr);
 }
 
 void round_tables_f64(const StepTables &in, int n_plaq, std::vector<RotParam<double>> &rot,
