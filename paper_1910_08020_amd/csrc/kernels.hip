@@ -92,19 +92,10 @@ __device__ __forceinline__ uint32_t link_set(int q, const uint32_t *tab)
     return tab[(q >> 3) * 256 + (1 << (q & 7))];
 }
 
-template <typename C>
-__device__ __forceinline__ C cmul(C a, C b)
-{
-    C r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
-
 __device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// a * b for a phase-table entry b.  Over small time steps b.x lies within a few ulps of
+// a * b for a phase factor b (a table entry or an R_z gate).  Over small time steps b.x lies within a few ulps of
 // +-1; a product by such a factor, rounded on its own, moves by a whole ulp or not at all,
 // the same way every step, and the norm of a complex64 state drifted by 1e-8 per step.
 // Here the products with b.x stay inside the FMA and are rounded once together with the
@@ -842,10 +833,11 @@ __global__ void k_gate_rx(cplx_t<T> *psi, int n, int q, T c, T s)
          p += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t i0 = ((p & ~lo) << 1) | (p & lo), i1 = i0 | (lo + 1);
         cplx_t<T> a0 = psi[i0], a1 = psi[i1], b0, b1;
-        b0.x = c * a0.x + s * a1.y;
-        b0.y = c * a0.y - s * a1.x;
-        b1.x = c * a1.x + s * a0.y;
-        b1.y = c * a1.y - s * a0.x;
+        // the products with c (within a few ulps of 1 for small angles) stay inside the FMA
+        b0.x = fma_r(c, a0.x, s * a1.y);
+        b0.y = fma_r(c, a0.y, -(s * a1.x));
+        b1.x = fma_r(c, a1.x, s * a0.y);
+        b1.y = fma_r(c, a1.y, -(s * a0.x));
         psi[i0] = b0;
         psi[i1] = b1;
     }
@@ -857,7 +849,7 @@ __global__ void k_gate_rz(cplx_t<T> *psi, int n, int q, cplx_t<T> e0, cplx_t<T> 
     const uint64_t dim = 1ull << n;
     for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < dim;
          b += (uint64_t)gridDim.x * blockDim.x)
-        psi[b] = cmul(psi[b], ((b >> q) & 1) ? e1 : e0);
+        psi[b] = cmul_ph(psi[b], ((b >> q) & 1) ? e1 : e0);
 }
 
 // controlled-Z: sign flip where qubits a and b are both |1>
