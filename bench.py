@@ -447,6 +447,36 @@ def precision(lgt):
     return out
 
 
+def long_run_precision(lgt, n=200_000, dt=4e-5):
+    """Complex64 against complex128 over the paper's kind of run (Sec. 2.2, 2.6): 3x3 from
+    the projected Z ground state, 2 x 10^5 substeps of t_s/n = 4e-5, the coupling ramped
+    from 0 to 2 or held at 1, first order: norm, state infidelity, and the largest error of
+    <U_p> and <sigma^x_l>."""
+    out = {}
+    for name, cx in (("ramp_g0_to_2", 2.0 * (np.arange(n) + 1) / n), ("constant_g1", np.ones(n))):
+        res = {}
+        for dtype, np_t in ((lgt.LGT_C64, np.complex64), (lgt.LGT_C128, np.complex128)):
+            ctx = lgt.lgt_create(2, [3, 3], 1, dtype)
+            try:
+                lgt.lgt_reset(ctx, lgt.LGT_INIT_ZGROUND, 0)
+                s = lgt.make_schedule(dt * n, n, ramp=lgt.LGT_RAMP_EXPLICIT,
+                                      cx=np.ascontiguousarray(cx), cz=np.ones(n))
+                lgt.lgt_evolve(ctx, s, lgt.LGT_ORDER_TROTTER, lgt.LGT_FORM_FUSED, 0, n)
+                info = lgt.lgt_info(ctx)
+                res[dtype] = (lgt.lgt_get_state(ctx, info["state_bytes"], np_t).astype(np.complex128),
+                              lgt.lgt_measure(ctx, lgt.LGT_OBS_PLAQ)[:info["n_plaq"]],
+                              lgt.lgt_measure(ctx, lgt.LGT_OBS_SIGMAX)[:info["n_links"]])
+            finally:
+                lgt.lgt_destroy(ctx)
+        (a, ua, xa), (b, ub, xb) = res[lgt.LGT_C64], res[lgt.LGT_C128]
+        na, nb = np.vdot(a, a).real, np.vdot(b, b).real
+        out[name] = {"substeps": n, "dt": dt, "norm_c64_minus_1": float(na - 1),
+                     "infidelity_c64_vs_c128": float(1 - abs(np.vdot(b, a)) ** 2 / (na * nb)),
+                     "plaq_err_max": float(np.max(np.abs(ua - ub))),
+                     "sigmax_err_max": float(np.max(np.abs(xa - xb)))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -543,6 +573,7 @@ def main():
         line["paper_scans"] = paper_scans(lgt)
         line["phase_estimation"] = phase_estimation(lgt)
         line["precision"] = precision(lgt)
+        line["precision_long_runs"] = long_run_precision(lgt)
     print(json.dumps(line), flush=True)
 
 
