@@ -435,6 +435,8 @@ hipError_t enqueue_fused_range(int dtype, int n, int n_plaq, const DevInst *dev_
 
 // graphs kept per context for batched evolutions
 static constexpr size_t kMaxGraphs = 64;
+// steps in the first chunk of FP32 phase rows a run rounds and uploads (then 2x, 4x, ...)
+static constexpr int kFirstChunk = 32;
 
 static hipError_t enqueue_fused(lgt_ctx *c, const DevInst *dev_inst, int n_inst, int count,
                                 int pre_phase, const uint8_t *forms)
@@ -849,7 +851,6 @@ lgt_status lgt_evolve(lgt_ctx *c, const lgt_schedule *sched, lgt_order order, lg
 static lgt_status evolve_fused(lgt_ctx *c, double dt, const std::vector<double> &cx,
                                const std::vector<double> &cz, lgt_order order)
 {
-    constexpr int kFirstChunk = 32;
     const Lattice &lat = c->lat;
     const int64_t count = (int64_t)cx.size();
     if (count > (1 << 24)) return fail(c, LGT_E_INVALID, "too many steps in one call");
@@ -1486,15 +1487,32 @@ lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule
     if (s) return fail(nullptr, s, c0->err);
     if (count == 0) return LGT_OK;
     // every instance's tables in one staging block, built on several host threads (the
-    // FP32 rounding of a 2000-step table takes milliseconds per instance)
+    // FP32 rounding of a 2000-step table takes milliseconds per instance).  Complex64 runs of
+    // tile passes round and upload their phase rows in chunks of 32, 64, 128, ... steps,
+    // each chunk's launches enqueued as soon as its rows are staged, as a single run does;
+    // a batch replayed from a graph, or run by the one-kernel small-state path, rounds its
+    // tables whole first.
+    const Lattice &lat = c0->lat;
+    const bool graph = c0->use_graphs && !c0->profiling && c0->stream;
+    const bool piped = c0->dtype == LGT_C64 && !graph && !small_supported(c0->dtype, lat.n_links);
     std::vector<Tables> tbs(n_inst);
     std::vector<StepTables> sts(n_inst);
     std::vector<std::string> whys(n_inst);
+    std::vector<std::vector<long double>> gains(n_inst);
     parallel_for(n_inst, [&](int i) {
         double dt;
         std::vector<double> cx, cz;
         whys[i] = schedule_coeffs(&scheds[i], first_step, count, dt, cx, cz);
-        if (whys[i].empty()) make_tables(c0->lat, c0->dtype, dt, cx, cz, orders[i], sts[i], tbs[i]);
+        if (!whys[i].empty()) return;
+        if (!piped) {
+            make_tables(lat, c0->dtype, dt, cx, cz, orders[i], sts[i], tbs[i]);
+            return;
+        }
+        build_step_tables(lat.n_links, lat.n_plaq, dt, cx.data(), cz.data(), (int)count, orders[i], sts[i]);
+        round_rot_f32(sts[i], lat.n_links, tbs[i].rf, gains[i]);
+        tbs[i].pf.assign((size_t)sts[i].n_phase * (lat.n_plaq + 1), Cplx<float>{});
+        tbs[i].rot_bytes = tbs[i].rf.size() * sizeof(RotParam<float>);
+        tbs[i].ph_bytes = tbs[i].pf.size() * sizeof(Cplx<float>);
     });
     std::vector<uint8_t> forms;
     for (int i = 0; i < n_inst; ++i) {
@@ -1516,7 +1534,7 @@ lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule
     std::vector<DevInst> di(n_inst);
     for (int i = 0; i < n_inst; ++i) {
         std::memcpy(stg + i * (rb + pb), rot_ptr(tbs[i], c0->dtype), tbs[i].rot_bytes);
-        std::memcpy(stg + i * (rb + pb) + rb, ph_ptr(tbs[i], c0->dtype), tbs[i].ph_bytes);
+        if (!piped) std::memcpy(stg + i * (rb + pb) + rb, ph_ptr(tbs[i], c0->dtype), tbs[i].ph_bytes);
         di[i].psi = ctxs[i]->state;
         di[i].rot = dev + i * (rb + pb);
         di[i].phase = dev + i * (rb + pb) + rb;
@@ -1526,45 +1544,81 @@ lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule
         di[i].n_total = (int)count;
     }
     std::memcpy(stg + (rb + pb) * n_inst, di.data(), sizeof(DevInst) * n_inst);
-    if (hipMemcpyAsync(dev, stg, total, hipMemcpyHostToDevice, c0->stream) != hipSuccess ||
-        hipEventRecord(c0->stage_free, c0->stream) != hipSuccess)
-        return fail(nullptr, LGT_E_DEVICE, "batch upload");
     const DevInst *dinst = (const DevInst *)(dev + (rb + pb) * n_inst);
     hipError_t e = hipSuccess;
-    // the null stream cannot be captured: batches on it launch directly
-    if (c0->use_graphs && !c0->profiling && c0->stream) {
-        // the launches depend only on this key (the tables and state pointers are read
-        // from the instance array on the device): the same key replays the same graph
-        std::string key = std::to_string(n_inst) + ":" + std::to_string(count) + ":" +
-                          std::to_string(c0->plan) + ":" + std::to_string(st.pre_phase) + ":" +
-                          std::to_string((uintptr_t)dinst) + ":";
-        key.append((const char *)forms.data(), forms.size());
-        auto it = c0->graphs.find(key);
-        if (it == c0->graphs.end() && c0->graphs.size() >= kMaxGraphs) {
-            // a bounded cache: drop every graph once the last launch of one has ended
-            if ((e = hipStreamSynchronize(c0->stream)) != hipSuccess)
-                return fail(nullptr, LGT_E_DEVICE, std::string("batch sync: ") + hipGetErrorString(e));
-            for (auto &g : c0->graphs) (void)hipGraphExecDestroy(g.second);
-            c0->graphs.clear();
+    if (piped) {
+        // link rows and the instance array first, then the phase rows chunk by chunk
+        for (int i = 0; i < n_inst && e == hipSuccess; ++i)
+            e = hipMemcpyAsync(dev + i * (rb + pb), stg + i * (rb + pb), tbs[i].rot_bytes,
+                               hipMemcpyHostToDevice, c0->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void *)dinst, stg + (rb + pb) * n_inst, sizeof(DevInst) * n_inst,
+                               hipMemcpyHostToDevice, c0->stream);
+        const int pre = st.pre_phase, steps = (int)count;
+        const size_t ph_row = sizeof(Cplx<float>) * (lat.n_plaq + 1);
+        std::vector<PhaseRounding> prs(n_inst);
+        FusedCursor cur;
+        for (int j0 = 0, len = kFirstChunk; j0 < steps && e == hipSuccess; j0 += len, len *= 2) {
+            const int j1 = (int)std::min<int64_t>(steps, (int64_t)j0 + len);
+            // phase rows read by the launches of steps [j0, j1) (as in a single run)
+            const int k0 = j0 == 0 ? 0 : j0 + pre, k1 = j1 + pre;
+            parallel_for(n_inst, [&](int i) {
+                round_phase_f32(sts[i], lat.n_plaq, gains[i], k0, k1, tbs[i].pf, prs[i]);
+                std::memcpy(stg + i * (rb + pb) + rb + ph_row * k0,
+                            (const char *)tbs[i].pf.data() + ph_row * k0, ph_row * (k1 - k0));
+            });
+            for (int i = 0; i < n_inst && e == hipSuccess; ++i)
+                e = hipMemcpyAsync(dev + i * (rb + pb) + rb + ph_row * k0,
+                                   stg + i * (rb + pb) + rb + ph_row * k0, ph_row * (k1 - k0),
+                                   hipMemcpyHostToDevice, c0->stream);
+            if (e == hipSuccess)
+                e = enqueue_fused_range(c0->dtype, lat.n_links, lat.n_plaq, dinst, n_inst, steps, j0,
+                                        j1, pre ? 0 : -1, pre, forms.data(), c0->plan, c0->stream,
+                                        c0, cur);
         }
-        if (it == c0->graphs.end()) {
-            hipGraph_t graph = nullptr;
-            hipGraphExec_t exec = nullptr;
-            e = hipStreamBeginCapture(c0->stream, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                const hipError_t el = enqueue_fused(c0, dinst, n_inst, (int)count, st.pre_phase, forms.data());
-                e = hipStreamEndCapture(c0->stream, &graph);
-                if (el != hipSuccess) e = el;
-            }
-            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            if (graph) (void)hipGraphDestroy(graph);
-            if (e == hipSuccess) it = c0->graphs.emplace(key, exec).first;
+        if (e == hipSuccess) e = hipEventRecord(c0->stage_free, c0->stream);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(c0->stream);
+            return fail(nullptr, LGT_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
         }
-        if (e == hipSuccess) e = hipGraphLaunch(it->second, c0->stream);
     } else {
-        e = enqueue_fused(c0, dinst, n_inst, (int)count, st.pre_phase, forms.data());
+        if (hipMemcpyAsync(dev, stg, total, hipMemcpyHostToDevice, c0->stream) != hipSuccess ||
+            hipEventRecord(c0->stage_free, c0->stream) != hipSuccess)
+            return fail(nullptr, LGT_E_DEVICE, "batch upload");
+        if (graph) {
+            // the launches depend only on this key (the tables and state pointers are read
+            // from the instance array on the device): the same key replays the same graph
+            std::string key = std::to_string(n_inst) + ":" + std::to_string(count) + ":" +
+                              std::to_string(c0->plan) + ":" + std::to_string(st.pre_phase) + ":" +
+                              std::to_string((uintptr_t)dinst) + ":";
+            key.append((const char *)forms.data(), forms.size());
+            auto it = c0->graphs.find(key);
+            if (it == c0->graphs.end() && c0->graphs.size() >= kMaxGraphs) {
+                // a bounded cache: drop every graph once the last launch of one has ended
+                if ((e = hipStreamSynchronize(c0->stream)) != hipSuccess)
+                    return fail(nullptr, LGT_E_DEVICE, std::string("batch sync: ") + hipGetErrorString(e));
+                for (auto &g : c0->graphs) (void)hipGraphExecDestroy(g.second);
+                c0->graphs.clear();
+            }
+            if (it == c0->graphs.end()) {
+                hipGraph_t hg = nullptr;
+                hipGraphExec_t exec = nullptr;
+                e = hipStreamBeginCapture(c0->stream, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    const hipError_t el = enqueue_fused(c0, dinst, n_inst, (int)count, st.pre_phase, forms.data());
+                    e = hipStreamEndCapture(c0->stream, &hg);
+                    if (el != hipSuccess) e = el;
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&exec, hg, nullptr, nullptr, 0);
+                if (hg) (void)hipGraphDestroy(hg);
+                if (e == hipSuccess) it = c0->graphs.emplace(key, exec).first;
+            }
+            if (e == hipSuccess) e = hipGraphLaunch(it->second, c0->stream);
+        } else {
+            e = enqueue_fused(c0, dinst, n_inst, (int)count, st.pre_phase, forms.data());
+        }
+        if (e != hipSuccess) return fail(nullptr, LGT_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     }
-    if (e != hipSuccess) return fail(nullptr, LGT_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     // the other contexts must not race ahead of the shared launches
     for (int i = 1; i < n_inst; ++i)
         if (ctxs[i]->stream != c0->stream && hipStreamSynchronize(c0->stream) != hipSuccess)
