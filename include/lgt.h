@@ -211,7 +211,13 @@ typedef struct {
  * merged into one phase (they commute, as in the rewritten product of
  * Sec. 2.2); a call starts and ends with a half step, so splitting a run into
  * several calls gives the same state up to rounding.  The schedule's
- * coefficient tables are computed on the host in FP64.
+ * coefficient tables are computed on the host in FP64.  A complex64 context
+ * rounds them to FP32 so that the phases undo the link layers' norm gains
+ * exactly over the call, and the call ends with the norm it started with to
+ * FP32 rounding; only when the first rotations of a run are smaller than an
+ * FP32 ulp of the amplitudes (steps of ~1e-5 from coupling 0) does the norm
+ * move, by ~1e-3 over 10^5 steps, which expectation values divide out (the
+ * norm itself then needs a complex128 context).
  * Errors: LGT_E_INVALID for a bad schedule or a step range outside
  * [0, n_steps); LGT_E_UNSUPPORTED for an unknown form.
  */
