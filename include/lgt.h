@@ -407,8 +407,11 @@ const char *lgt_last_error(const lgt_ctx *ctx);
  * but every pass is one launch over all instances, and small lattices (N <= 12) run
  * every step of the range in a single launch with the state held on chip.
  * Work is enqueued on ctxs[0]'s stream; the other contexts' streams are
- * synchronised first.  Errors as lgt_evolve; LGT_E_INVALID if the contexts do
- * not share lattice and dtype.
+ * synchronised first.  States that each fit in 160 MiB but together do not (e.g.
+ * 24-link complex64 states, 128 MiB each) run in groups of at most 160 MiB, one group
+ * after the other on its first context's stream, the call waiting for each group, so
+ * that a group's state stays in the 256 MB Infinity Cache between passes.  Errors as
+ * lgt_evolve; LGT_E_INVALID if the contexts do not share lattice and dtype.
  */
 lgt_status lgt_batch_evolve(int n, lgt_ctx *const *ctxs, const lgt_schedule *scheds,
                             const lgt_order *orders, int64_t first_step, int64_t count);

@@ -481,3 +481,21 @@ def test_chunked_tables_equal_whole_table(order, dtype):
     with gpu_ctx(d, L, dtype) as c:
         lgt.lgt_evolve(c, s, order, lgt.LGT_FORM_FUSED, 0, n)
         assert np.array_equal(get_state(c), whole)
+
+
+def test_batch_beyond_the_cache_runs_in_groups_equal_to_single_runs():
+    """Three 24-link complex64 states (128 MiB each) exceed the Infinity Cache together and
+    run one after another inside the batch call; each equals its single run bit for bit."""
+    d, L, n = 3, (2, 2, 2), 12
+    scheds = [lgt.make_schedule(0.05 * n, n, lam, 1.0) for lam in (0.2, 1.0, 25.0)]
+    ctxs = [lgt.lgt_create(d, list(L), 1, C64) for _ in scheds]
+    try:
+        lgt.lgt_batch_evolve(ctxs, scheds, [SYM] * len(scheds), 0, n)
+        batched = [get_state(c) for c in ctxs]
+    finally:
+        for c in ctxs:
+            lgt.lgt_destroy(c)
+    for s, psi in zip(scheds, batched):
+        with gpu_ctx(d, L, C64) as ctx:
+            lgt.lgt_evolve(ctx, s, SYM, lgt.LGT_FORM_FUSED, 0, n)
+            assert np.array_equal(get_state(ctx), psi)
