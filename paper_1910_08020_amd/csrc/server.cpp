@@ -9,6 +9,7 @@
 // memory goes back to the budget.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -130,6 +131,8 @@ struct lgt_server {
 namespace {
 
 constexpr int kParts = 2048 * (kMaxPlaq + 1);
+// state bytes of one launch group that stay in the 256 MB Infinity Cache between passes
+constexpr size_t kCacheStateBytes = (size_t)160 << 20;
 
 size_t elem_bytes(int dtype) { return dtype == LGT_C64 ? 8 : 16; }
 
@@ -304,11 +307,22 @@ void worker_loop(lgt_server *s)
             act = s->active;
         }
         if (act.empty()) continue;
-        // one batched launch sequence per lattice shape
+        // one batched launch sequence per lattice shape, split into groups whose states
+        // fit the Infinity Cache together when each state does (the groups run one after
+        // the other on the server's stream)
         std::map<Shape, std::vector<Run *>> groups;
         for (Run *r : act) groups[r->shape].push_back(r);
+        std::vector<std::vector<Run *>> lgroups;
+        for (auto &g : groups) {
+            const size_t sb = g.second[0]->sr->state_bytes;
+            const size_t per = sb <= kCacheStateBytes ? std::max<size_t>(1, kCacheStateBytes / sb)
+                                                      : g.second.size();
+            for (size_t i = 0; i < g.second.size(); i += per)
+                lgroups.emplace_back(g.second.begin() + i,
+                                     g.second.begin() + std::min(g.second.size(), i + per));
+        }
         size_t need = 0;
-        for (auto &g : groups) need += ((g.second.size() * sizeof(DevInst)) + 255) & ~(size_t)255;
+        for (auto &g : lgroups) need += ((g.size() * sizeof(DevInst)) + 255) & ~(size_t)255;
         if (s->inst_cap < need) {
             (void)hipStreamSynchronize(s->stream);
             if (s->inst_dev) (void)hipFree(s->inst_dev);
@@ -325,12 +339,12 @@ void worker_loop(lgt_server *s)
         std::vector<char> host(need);
         size_t off = 0;
         bool dev_fail = false;
-        std::vector<std::pair<size_t, std::pair<Shape, int>>> launches;
-        for (auto &g : groups) {
-            const ShapeRes &sr = *g.second[0]->sr;
+        std::vector<size_t> offs;
+        for (auto &g : lgroups) {
+            const ShapeRes &sr = *g[0]->sr;
             DevInst *di = (DevInst *)(host.data() + off);
-            for (size_t i = 0; i < g.second.size(); ++i) {
-                Run *r = g.second[i];
+            for (size_t i = 0; i < g.size(); ++i) {
+                Run *r = g[i];
                 di[i] = DevInst{};
                 di[i].psi = r->psi;
                 di[i].rot = r->tables;
@@ -340,23 +354,22 @@ void worker_loop(lgt_server *s)
                 di[i].ph0 = r->step + r->pre;
                 di[i].n_total = r->n_total;
             }
-            launches.push_back({off, {g.first, (int)g.second.size()}});
-            off += ((g.second.size() * sizeof(DevInst)) + 255) & ~(size_t)255;
+            offs.push_back(off);
+            off += ((g.size() * sizeof(DevInst)) + 255) & ~(size_t)255;
         }
         if (stage_to_device(s, s->inst_dev, host.data(), need) != hipSuccess) dev_fail = true;
-        for (auto &l : launches) {
-            if (dev_fail) break;
-            const ShapeRes &sr = *groups[l.second.first][0]->sr;
+        for (size_t gi = 0; gi < lgroups.size() && !dev_fail; ++gi) {
+            const std::vector<Run *> &g = lgroups[gi];
+            const ShapeRes &sr = *g[0]->sr;
             int steps = 0;
-            for (Run *r : groups[l.second.first]) steps = std::max(steps, r->n_total - r->step);
+            for (Run *r : g) steps = std::max(steps, r->n_total - r->step);
             steps = std::min(steps, s->chunk);
             std::vector<uint8_t> forms(steps, 0);
-            for (Run *r : groups[l.second.first])
+            for (Run *r : g)
                 for (int j = 0; j < steps && r->step + j < r->n_total; ++j) forms[j] |= r->forms[r->step + j];
-            if (enqueue_fused_steps(l.second.first.dtype, sr.lat.n_links, sr.lat.n_plaq,
-                                    (const DevInst *)((char *)s->inst_dev + l.first),
-                                    l.second.second, steps, -1, 0, forms.data(), 0, s->stream,
-                                    nullptr) != hipSuccess)
+            if (enqueue_fused_steps(g[0]->shape.dtype, sr.lat.n_links, sr.lat.n_plaq,
+                                    (const DevInst *)((char *)s->inst_dev + offs[gi]), (int)g.size(),
+                                    steps, -1, 0, forms.data(), 0, s->stream, nullptr) != hipSuccess)
                 dev_fail = true;
         }
         if (!dev_fail && hipStreamSynchronize(s->stream) != hipSuccess) dev_fail = true;
