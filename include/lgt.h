@@ -459,9 +459,12 @@ typedef struct {
  * lgt_server_create: a server that keeps admitted runs resident on the
  * current device, admitting them while their state plus scratch fits in
  * hbm_budget bytes and a slot (max_slots) is free.  A worker thread advances
- * every admitted run by chunk_steps steps per round, one batched launch per
- * lattice shape, so runs that arrive while others are in flight join at the
- * next round (continuous batching).  Runs finish independently.
+ * every admitted run per round, one batched launch sequence per lattice shape
+ * (in groups whose states fit the Infinity Cache together), so runs that arrive
+ * while others are in flight join at the next round (continuous batching).  A
+ * run advances chunk_steps steps per round if its state is 128 MiB or more, and
+ * up to 4x as many for smaller states, whose steps cost about a launch each; the
+ * count depends on the run's shape only.  Runs finish independently.
  */
 lgt_status lgt_server_create(size_t hbm_budget, int max_slots, int chunk_steps,
                              lgt_server **out);
