@@ -170,6 +170,74 @@ def test_no_link_term_pure_phase(order):
     assert np.max(np.abs(got - want)) < 1e-12
 
 
+@pytest.mark.parametrize("order", [1, 2])
+def test_midpoint_rule_pure_phase(order):
+    """The midpoint option s_j = (j - 1/2)/n with h_x = 0: sum_j dt s_j = dt n / 2 = T / 2
+    exactly, so psi_b(T) = psi_b(0) exp(i h_p (T/2) u(b)).  The right-end rule of Sec. 2.2
+    gives dt (n+1)/2 instead, so a schedule on the wrong rule fails by h_p dt / 2."""
+    N = L22.N
+    h_p, T, n = 1.3, 2.0, 25
+    dt, cx, cz = oracle.schedule_plaquette_ramp(T, n, 0.0, h_p, midpoint=True)
+    psi0 = _rand_state(N, 8)
+    got = oracle.evolve(psi0.copy(), L22, dt, cx, cz, order)
+    u = np.real(np.diag(ed.h_plaq(N, L22.plaq)))
+    want = psi0 * np.exp(1j * h_p * T / 2 * u)
+    assert np.max(np.abs(got - want)) < 1e-12
+    # the coupling ramp on the midpoint rule: sum_j g_j = n (g0 + g1) / 2, so with only the
+    # link term (cz dropped by a zero plaquette weight) |0...0> precesses by the mean coupling
+    dt, cx, cz = oracle.schedule_coupling_ramp(T, n, 0.4, 1.6, midpoint=True)
+    psi = oracle.evolve(oracle.basis_state(N, 0), L22, dt, cx, 0.0 * cz, order)
+    for q in range(N):
+        assert abs(oracle.expect_z(psi, N, [q]) - np.cos(2 * 1.0 * T)) < 1e-12
+
+
+def _h_apply(psi, N, plaq, cx, cz):
+    """H psi for H = -cx sum_l sigma^x_l - cz sum_p U_p, each Pauli factor applied by
+    reshaping the amplitude array around its qubit axis (bit q of the index is qubit q)."""
+    out = np.zeros_like(psi)
+    for q in range(N):
+        v = psi.reshape(1 << (N - 1 - q), 2, 1 << q)
+        out -= cx * v[:, ::-1, :].reshape(-1)
+    for p in plaq:
+        w = psi.copy()
+        for q in p:
+            v = w.reshape(1 << (N - 1 - int(q)), 2, 1 << int(q))
+            v[:, 1, :] *= -1
+        out -= cz * w
+    return out
+
+
+@pytest.mark.parametrize("d,L", [(2, (2, 2)), (2, (2, 3))], ids=["2x2", "2x3"])
+def test_readout_energy_matches_exact_expectation(d, L):
+    """readout(): energy = <psi|H|psi>/<psi|psi> for random (unnormalised) states, with H
+    built from Pauli factors (a dense Kronecker matrix on 2x2), and every reported
+    observable against its operator: <U_p>, <sigma^x_l>, <sigma^z_l>, <G_i>, the norm."""
+    lat = Lattice(d, L)
+    N = lat.N
+    for seed, (cx, cz) in ((11, (0.7, 1.3)), (12, (-1.9, 0.4)), (13, (2.5, -0.8))):
+        psi = 1.7 * _rand_state(N, seed)
+        r = oracle.readout(psi, lat, cx, cz)
+        n2 = np.vdot(psi, psi).real
+        if N <= 8:
+            H = ed.hamiltonian(N, lat.plaq, cx, cz)
+            want = np.vdot(psi, H @ psi).real / n2
+        else:
+            want = np.vdot(psi, _h_apply(psi, N, lat.plaq, cx, cz)).real / n2
+        assert abs(r["energy"] - want) < 1e-12 * max(1.0, abs(want))
+        assert abs(r["norm"] - n2) < 1e-12 * n2
+        if N <= 8:
+            for p, v in zip(lat.plaq, r["plaq"]):
+                assert abs(v - np.vdot(psi, ed.pauli_product(N, p, ed.SZ) @ psi).real / n2) < 1e-13
+            for q in range(N):
+                assert abs(r["sigma_x"][q] - np.vdot(psi, ed.op_on(N, q, ed.SX) @ psi).real / n2) < 1e-13
+                assert abs(r["sigma_z"][q] - np.vdot(psi, ed.op_on(N, q, ed.SZ) @ psi).real / n2) < 1e-13
+            for s, v in zip(lat.stars, r["stars"]):
+                assert abs(v - np.vdot(psi, ed.pauli_product(N, s, ed.SX) @ psi).real / n2) < 1e-13
+    # an eigenstate: the energy of |+>^N under the link term alone is -cx N
+    r = oracle.readout(oracle.plus_state(N), lat, 0.9, 0.0)
+    assert abs(r["energy"] + 0.9 * N) < 1e-12
+
+
 def test_plus_state_stationary_without_plaquettes():
     """|+>^N is an eigenstate of sum sigma^x: only a global phase e^{i N h_x T}."""
     N = L33.N
