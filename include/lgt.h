@@ -469,17 +469,48 @@ typedef struct {
 lgt_status lgt_server_create(size_t hbm_budget, int max_slots, int chunk_steps,
                              lgt_server **out);
 
-/* lgt_server_submit: queue a run; LGT_E_OOM if it can never fit the budget. */
+/* lgt_server_submit: queue a run.  The request (and its explicit coefficient arrays) is
+ * copied and its tables are built on the calling thread.  LGT_E_INVALID for a bad request,
+ * including n_steps < 1 or > 2^24 (checked before anything is read from cx / cz);
+ * LGT_E_OOM if the run can never fit the budget or a host allocation fails. */
 lgt_status lgt_server_submit(lgt_server *srv, const lgt_request *req, uint64_t *ticket);
 
-/* lgt_server_poll: non-blocking; out->done = 0 while the run is pending. */
+/* lgt_server_poll: non-blocking; out->done = 0 while the run is queued or running.
+ * A finished result is delivered once: the poll or wait that returns it with done = 1 also
+ * releases the ticket, and later calls with that ticket give LGT_E_INVALID. */
 lgt_status lgt_server_poll(lgt_server *srv, uint64_t ticket, lgt_result *out);
 
-/* lgt_server_wait: block until the run is done (timeout_ms < 0: no limit). */
+/* lgt_server_wait: block until the run is done (timeout_ms < 0: no limit); LGT_E_BUSY (and
+ * out->done = 0) if the time runs out first.  Delivers and releases like lgt_server_poll. */
 lgt_status lgt_server_wait(lgt_server *srv, uint64_t ticket, double timeout_ms,
                            lgt_result *out);
 
-/* lgt_server_destroy: finish in-flight runs, stop the worker, free memory. */
+/* lgt_server_cancel: a queued run is dropped at once; an admitted run stops at the next
+ * round boundary and gives back its slot and memory.  Its result then comes with
+ * done = 1 and status LGT_E_STATE.  A run that completes in the round under way keeps its
+ * result.  LGT_E_INVALID for an unknown or already delivered ticket, LGT_E_STATE if the
+ * run has already finished (its result is waiting to be delivered). */
+lgt_status lgt_server_cancel(lgt_server *srv, uint64_t ticket);
+
+typedef struct {
+    size_t budget_bytes, used_bytes;   /* admission budget and the footprint admitted now */
+    int pending, active;               /* queued runs, admitted runs                        */
+    uint64_t completed, failed, cancelled;  /* finished runs by outcome                    */
+    uint64_t undelivered;              /* finished results not yet returned by poll / wait */
+} lgt_server_stats_t;
+
+/* lgt_server_stats: a snapshot of the server's queue, memory and outcome counters. */
+lgt_status lgt_server_stats(lgt_server *srv, lgt_server_stats_t *out);
+
+/* lgt_server_inject_fault: testing hook for the failure path of a round.  The launch group
+ * that holds the (queued or admitted) run next reports a failed launch without launching
+ * anything: every run of that group ends with LGT_E_DEVICE and gives back its slot and
+ * memory, while the other groups of the round go on.  LGT_E_INVALID if the ticket is not
+ * queued or running. */
+lgt_status lgt_server_inject_fault(lgt_server *srv, uint64_t ticket);
+
+/* lgt_server_destroy: finish the admitted runs, cancel the queued ones, stop the worker
+ * and free the server's memory.  Undelivered results are dropped with it. */
 lgt_status lgt_server_destroy(lgt_server *srv);
 
 #ifdef __cplusplus

@@ -10,13 +10,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -69,6 +72,8 @@ struct Run {
     std::vector<uint8_t> forms;   // per step: 1 tan-form, 2 cot-form link rotation
     double cx_last = 0, cz_last = 0;
     std::vector<char> blob;        // host copy of the tables, built on the submitting thread
+    std::atomic<bool> cancel{false};        // stop at the next round boundary (lgt_server_cancel)
+    std::atomic<bool> inject_fault{false};  // test hook: the run's next launch group fails
 };
 
 // the run's rot | phase tables (rounded for its dtype), built when it is submitted so that
@@ -115,9 +120,11 @@ struct lgt_server {
     std::deque<Run *> pending;
     std::vector<Run *> active;
     std::map<uint64_t, lgt_result> results;
+    std::map<uint64_t, Run *> live;   // queued and admitted runs by ticket
     std::map<Shape, ShapeRes> shapes;
     uint64_t next_ticket = 1;
     bool stop = false;
+    uint64_t n_ok = 0, n_failed = 0, n_cancelled = 0;   // finished runs by outcome
     std::thread worker;
     // device scratch owned by the worker
     DevInst *inst_dev = nullptr;
@@ -132,6 +139,8 @@ struct lgt_server {
 namespace {
 
 constexpr int kParts = 2048 * (kMaxPlaq + 1);
+// longest run (and round) the server takes, the step limit of one lgt_evolve call
+constexpr int64_t kMaxRunSteps = (int64_t)1 << 24;
 // state bytes of one launch group that stay in the 256 MB Infinity Cache between passes
 constexpr size_t kCacheStateBytes = (size_t)160 << 20;
 
@@ -146,7 +155,8 @@ int round_steps(int chunk, size_t state_bytes)
 {
     const double t_step = std::max(7e-6, 2.0 * (double)state_bytes / 5e12);
     const double ref = 2.0 * (double)((size_t)128 << 20) / 5e12;
-    return chunk * (int)std::lround(std::min(4.0, std::max(1.0, ref / t_step)));
+    const int64_t k = std::lround(std::min(4.0, std::max(1.0, ref / t_step)));
+    return (int)std::min<int64_t>((int64_t)chunk * k, kMaxRunSteps);
 }
 
 size_t elem_bytes(int dtype) { return dtype == LGT_C64 ? 8 : 16; }
@@ -238,6 +248,10 @@ void finish(lgt_server *s, Run *r, lgt_status st, const lgt_result *res_in)
         std::lock_guard<std::mutex> lk(s->mu);
         if (r->admitted) s->used -= r->footprint;
         s->results[r->ticket] = res;
+        s->live.erase(r->ticket);
+        if (st == LGT_OK) ++s->n_ok;
+        else if (st == LGT_E_STATE) ++s->n_cancelled;
+        else ++s->n_failed;
     }
     s->cv_done.notify_all();
     delete r;
@@ -273,11 +287,18 @@ lgt_status admit(lgt_server *s, Run *r)
     return LGT_OK;
 }
 
+// finish every run of `runs` with `st`, under no lock; the server's lists are updated by
+// the caller
+void finish_all(lgt_server *s, const std::vector<Run *> &runs, lgt_status st)
+{
+    for (Run *r : runs) finish(s, r, st, nullptr);
+}
+
 void worker_loop(lgt_server *s)
 {
     (void)hipSetDevice(s->device);
     for (;;) {
-        std::vector<Run *> newly;
+        std::vector<Run *> newly, cancelled;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
@@ -291,11 +312,17 @@ void worker_loop(lgt_server *s)
                     res.status = LGT_E_STATE;
                     res.latency_ms = ms_between(r->t_submit, Clock::now());
                     s->results[r->ticket] = res;
+                    s->live.erase(r->ticket);
+                    ++s->n_cancelled;
                     delete r;
                 }
                 s->cv_done.notify_all();
                 return;
             }
+            // runs cancelled while admitted stop at this round boundary
+            std::vector<Run *> keep;
+            for (Run *r : s->active) (r->cancel ? cancelled : keep).push_back(r);
+            s->active.swap(keep);
             // FIFO admission by slot and HBM footprint
             while (!s->stop && !s->pending.empty() &&
                    (int)(s->active.size() + newly.size()) < s->max_slots &&
@@ -307,6 +334,7 @@ void worker_loop(lgt_server *s)
                 newly.push_back(r);
             }
         }
+        finish_all(s, cancelled, LGT_E_STATE);
         for (Run *r : newly) {
             lgt_status st = admit(s, r);
             if (st != LGT_OK) {
@@ -344,7 +372,7 @@ void worker_loop(lgt_server *s)
             s->inst_dev = nullptr;
             s->inst_cap = 0;
             if (hipMalloc((void **)&s->inst_dev, need * 2) != hipSuccess) {
-                for (Run *r : act) finish(s, r, LGT_E_OOM, nullptr);
+                finish_all(s, act, LGT_E_OOM);
                 std::lock_guard<std::mutex> lk(s->mu);
                 s->active.clear();
                 continue;
@@ -353,7 +381,6 @@ void worker_loop(lgt_server *s)
         }
         std::vector<char> host(need);
         size_t off = 0;
-        bool dev_fail = false;
         std::vector<size_t> offs;
         for (auto &g : lgroups) {
             const ShapeRes &sr = *g[0]->sr;
@@ -372,44 +399,123 @@ void worker_loop(lgt_server *s)
             offs.push_back(off);
             off += ((g.size() * sizeof(DevInst)) + 255) & ~(size_t)255;
         }
-        if (stage_to_device(s, s->inst_dev, host.data(), need) != hipSuccess) dev_fail = true;
-        for (size_t gi = 0; gi < lgroups.size() && !dev_fail; ++gi) {
+        // a group whose launches fail ends its own runs; the others go on.  A failed upload
+        // or stream synchronisation ends every run of the round.
+        bool round_fail = stage_to_device(s, s->inst_dev, host.data(), need) != hipSuccess;
+        std::vector<char> group_fail(lgroups.size(), 0);
+        for (size_t gi = 0; gi < lgroups.size() && !round_fail; ++gi) {
             const std::vector<Run *> &g = lgroups[gi];
             const ShapeRes &sr = *g[0]->sr;
             int steps = 0;
             for (Run *r : g) steps = std::max(steps, r->n_total - r->step);
             steps = std::min(steps, round_steps(s->chunk, sr.state_bytes));
             for (Run *r : g) r->adv = steps;
+            bool inject = false;
+            for (Run *r : g) inject = inject || r->inject_fault;
+            if (inject) {
+                // test hook: the group's launch reports a failure; nothing is launched
+                group_fail[gi] = 1;
+                continue;
+            }
             std::vector<uint8_t> forms(steps, 0);
             for (Run *r : g)
                 for (int j = 0; j < steps && r->step + j < r->n_total; ++j) forms[j] |= r->forms[r->step + j];
             if (enqueue_fused_steps(g[0]->shape.dtype, sr.lat.n_links, sr.lat.n_plaq,
                                     (const DevInst *)((char *)s->inst_dev + offs[gi]), (int)g.size(),
                                     steps, -1, 0, forms.data(), 0, s->stream, nullptr) != hipSuccess)
-                dev_fail = true;
+                group_fail[gi] = 1;
         }
-        if (!dev_fail && hipStreamSynchronize(s->stream) != hipSuccess) dev_fail = true;
+        if (!round_fail && hipStreamSynchronize(s->stream) != hipSuccess) round_fail = true;
         std::vector<Run *> still;
-        for (Run *r : act) {
-            if (dev_fail) {
-                finish(s, r, LGT_E_DEVICE, nullptr);
-                continue;
-            }
-            r->step = std::min(r->n_total, r->step + r->adv);
-            if (r->step >= r->n_total) {
-                lgt_result res{};
-                const bool ok = readout(s, r, res) == hipSuccess;
-                finish(s, r, ok ? LGT_OK : LGT_E_DEVICE, &res);
-            } else {
-                still.push_back(r);
+        for (size_t gi = 0; gi < lgroups.size(); ++gi) {
+            for (Run *r : lgroups[gi]) {
+                if (round_fail || group_fail[gi]) {
+                    finish(s, r, LGT_E_DEVICE, nullptr);
+                    continue;
+                }
+                r->step = std::min(r->n_total, r->step + r->adv);
+                if (r->step >= r->n_total) {
+                    lgt_result res{};
+                    const bool ok = readout(s, r, res) == hipSuccess;
+                    finish(s, r, ok ? LGT_OK : LGT_E_DEVICE, &res);
+                } else {
+                    still.push_back(r);
+                }
             }
         }
         std::lock_guard<std::mutex> lk(s->mu);
+        // runs cancelled during the round stay listed until the next round boundary
         s->active = still;
     }
 }
 
-lgt_status fail_null(const char *) { return LGT_E_INVALID; }
+// queue a run: validate and copy the request, build its tables on the caller's thread
+lgt_status submit_run(lgt_server *s, const lgt_request *req, uint64_t *ticket)
+{
+    Shape sh{};
+    sh.d = req->d;
+    sh.dtype = req->dtype;
+    for (int i = 0; i < 3; ++i) sh.L[i] = (i < req->d) ? req->L[i] : 1;
+    std::unique_ptr<Run> r(new Run());
+    r->t_submit = Clock::now();
+    r->shape = sh;
+    r->sched = req->sched;
+    r->order = req->order;
+    if (req->sched.ramp == LGT_RAMP_EXPLICIT) {
+        if (!req->sched.cx || !req->sched.cz) return LGT_E_INVALID;
+        r->cx_copy.assign(req->sched.cx, req->sched.cx + req->sched.n_steps);
+        r->cz_copy.assign(req->sched.cz, req->sched.cz + req->sched.n_steps);
+        r->sched.cx = r->cx_copy.data();
+        r->sched.cz = r->cz_copy.data();
+    }
+    double dt;
+    std::vector<double> cx, cz;
+    if (!schedule_coeffs(&r->sched, 0, r->sched.n_steps, dt, cx, cz).empty()) return LGT_E_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->shapes.find(sh);
+    if (it == s->shapes.end()) {
+        ShapeRes sr;
+        std::string why = build_lattice(req->d, req->L, sr.lat);
+        if (!why.empty())
+            return why.find("too many") != std::string::npos ? LGT_E_UNSUPPORTED : LGT_E_INVALID;
+        uint32_t tab[kParityBytes][256];
+        build_parity_tables(sr.lat, tab);
+        if (hipSetDevice(s->device) != hipSuccess || hipMalloc((void **)&sr.ptab_dev, sizeof tab) != hipSuccess)
+            return LGT_E_DEVICE;
+        if (hipMemcpy(sr.ptab_dev, tab, sizeof tab, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(sr.ptab_dev);
+            return LGT_E_DEVICE;
+        }
+        sr.state_bytes = ((size_t)1 << sr.lat.n_links) * elem_bytes(sh.dtype);
+        it = s->shapes.emplace(sh, std::move(sr)).first;
+    }
+    const ShapeRes &sr = it->second;
+    r->sr = &it->second;
+    const size_t steps = (size_t)r->sched.n_steps;
+    r->footprint = sr.state_bytes + steps * 2 * 8 * (sh.dtype == LGT_C64 ? 1 : 2) +
+                   (steps + 1) * (sr.lat.n_plaq + 1) * elem_bytes(sh.dtype) + 1024;
+    if (r->footprint > s->budget) return LGT_E_OOM;
+    // the tables are built here, on the caller's thread, outside the lock (the shape's
+    // lattice stays put in the map)
+    lk.unlock();
+    build_tables(sr.lat, sh.dtype, r.get(), cx, cz, dt);
+    lk.lock();
+    r->ticket = s->next_ticket++;
+    *ticket = r->ticket;
+    s->results[r->ticket] = lgt_result{};
+    s->live[r->ticket] = r.get();
+    s->pending.push_back(r.release());
+    lk.unlock();
+    s->cv_work.notify_one();
+    return LGT_OK;
+}
+
+// the queued or admitted run holding `ticket`, or null (call with the lock held)
+Run *find_run(lgt_server *s, uint64_t ticket)
+{
+    auto it = s->live.find(ticket);
+    return it == s->live.end() ? nullptr : it->second;
+}
 
 }  // namespace
 
@@ -418,12 +524,14 @@ extern "C" {
 lgt_status lgt_server_create(size_t hbm_budget, int max_slots, int chunk_steps, lgt_server **out)
 {
     if (!out || max_slots < 1 || max_slots > 65535 || chunk_steps < 1 || hbm_budget == 0)
-        return fail_null("bad server arguments");
+        return LGT_E_INVALID;
     *out = nullptr;
-    lgt_server *s = new lgt_server();
+    lgt_server *s = new (std::nothrow) lgt_server();
+    if (!s) return LGT_E_OOM;
     s->budget = hbm_budget;
     s->max_slots = max_slots;
-    s->chunk = chunk_steps;
+    // a round never needs more steps than the longest run takes
+    s->chunk = (int)std::min<int64_t>(chunk_steps, kMaxRunSteps);
     if (hipGetDevice(&s->device) != hipSuccess ||
         hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc((void **)&s->partials, sizeof(double) * kParts) != hipSuccess ||
@@ -447,74 +555,19 @@ lgt_status lgt_server_submit(lgt_server *s, const lgt_request *req, uint64_t *ti
     if (!s || !req || !ticket) return LGT_E_INVALID;
     if (req->dtype != LGT_C64 && req->dtype != LGT_C128) return LGT_E_INVALID;
     if (req->order != LGT_ORDER_TROTTER && req->order != LGT_ORDER_SYMMETRIC) return LGT_E_INVALID;
-    Shape sh{};
-    sh.d = req->d;
-    sh.dtype = req->dtype;
-    for (int i = 0; i < 3; ++i) sh.L[i] = (i < req->d) ? req->L[i] : 1;
-    Run *r = new Run();
-    r->t_submit = Clock::now();
-    r->shape = sh;
-    r->sched = req->sched;
-    r->order = req->order;
-    if (req->sched.ramp == LGT_RAMP_EXPLICIT) {
-        if (!req->sched.cx || !req->sched.cz || req->sched.n_steps < 1) {
-            delete r;
-            return LGT_E_INVALID;
-        }
-        r->cx_copy.assign(req->sched.cx, req->sched.cx + req->sched.n_steps);
-        r->cz_copy.assign(req->sched.cz, req->sched.cz + req->sched.n_steps);
-        r->sched.cx = r->cx_copy.data();
-        r->sched.cz = r->cz_copy.data();
-    }
-    double dt;
-    std::vector<double> cx, cz;
-    if (!schedule_coeffs(&r->sched, 0, r->sched.n_steps, dt, cx, cz).empty() ||
-        r->sched.n_steps > (1 << 24)) {
-        delete r;
+    // the step count is checked before anything is copied or built from it
+    if (req->sched.n_steps < 1 || req->sched.n_steps > kMaxRunSteps) return LGT_E_INVALID;
+    if (req->d < 2 || req->d > 3) return LGT_E_INVALID;
+    try {
+        return submit_run(s, req, ticket);
+    } catch (const std::bad_alloc &) {
+        return LGT_E_OOM;
+    } catch (...) {
         return LGT_E_INVALID;
     }
-    std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->shapes.find(sh);
-    if (it == s->shapes.end()) {
-        ShapeRes sr;
-        std::string why = build_lattice(req->d, req->L, sr.lat);
-        if (!why.empty()) {
-            delete r;
-            return why.find("too many") != std::string::npos ? LGT_E_UNSUPPORTED : LGT_E_INVALID;
-        }
-        uint32_t tab[kParityBytes][256];
-        build_parity_tables(sr.lat, tab);
-        if (hipSetDevice(s->device) != hipSuccess || hipMalloc((void **)&sr.ptab_dev, sizeof tab) != hipSuccess ||
-            hipMemcpy(sr.ptab_dev, tab, sizeof tab, hipMemcpyHostToDevice) != hipSuccess) {
-            delete r;
-            return LGT_E_DEVICE;
-        }
-        sr.state_bytes = ((size_t)1 << sr.lat.n_links) * elem_bytes(sh.dtype);
-        it = s->shapes.emplace(sh, std::move(sr)).first;
-    }
-    const ShapeRes &sr = it->second;
-    r->sr = &it->second;
-    const size_t steps = (size_t)r->sched.n_steps;
-    r->footprint = sr.state_bytes + steps * 2 * 8 * (sh.dtype == LGT_C64 ? 1 : 2) +
-                   (steps + 1) * (sr.lat.n_plaq + 1) * elem_bytes(sh.dtype) + 1024;
-    if (r->footprint > s->budget) {
-        delete r;
-        return LGT_E_OOM;
-    }
-    // the tables are built here, on the caller's thread, outside the lock (the shape's
-    // lattice stays put in the map)
-    lk.unlock();
-    build_tables(sr.lat, sh.dtype, r, cx, cz, dt);
-    lk.lock();
-    r->ticket = s->next_ticket++;
-    *ticket = r->ticket;
-    s->results[r->ticket] = lgt_result{};
-    s->pending.push_back(r);
-    lk.unlock();
-    s->cv_work.notify_one();
-    return LGT_OK;
 }
 
+// a finished result is handed out once: the call that returns it also releases the ticket
 lgt_status lgt_server_poll(lgt_server *s, uint64_t ticket, lgt_result *out)
 {
     if (!s || !out) return LGT_E_INVALID;
@@ -522,6 +575,7 @@ lgt_status lgt_server_poll(lgt_server *s, uint64_t ticket, lgt_result *out)
     auto it = s->results.find(ticket);
     if (it == s->results.end()) return LGT_E_INVALID;
     *out = it->second;
+    if (out->done) s->results.erase(it);
     return LGT_OK;
 }
 
@@ -538,7 +592,68 @@ lgt_status lgt_server_wait(lgt_server *s, uint64_t ticket, double timeout_ms, lg
     auto it = s->results.find(ticket);
     if (it == s->results.end()) return LGT_E_INVALID;
     *out = it->second;
-    return it->second.done ? LGT_OK : LGT_E_BUSY;
+    if (!out->done) return LGT_E_BUSY;
+    s->results.erase(it);
+    return LGT_OK;
+}
+
+lgt_status lgt_server_cancel(lgt_server *s, uint64_t ticket)
+{
+    if (!s) return LGT_E_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->results.find(ticket);
+    if (it == s->results.end()) return LGT_E_INVALID;
+    if (it->second.done) return LGT_E_STATE;
+    for (auto q = s->pending.begin(); q != s->pending.end(); ++q) {
+        if ((*q)->ticket != ticket) continue;
+        Run *r = *q;
+        s->pending.erase(q);
+        lgt_result res{};
+        res.done = 1;
+        res.status = LGT_E_STATE;
+        res.latency_ms = ms_between(r->t_submit, Clock::now());
+        res.queue_ms = res.latency_ms;
+        it->second = res;
+        s->live.erase(ticket);
+        ++s->n_cancelled;
+        delete r;
+        lk.unlock();
+        s->cv_done.notify_all();
+        return LGT_OK;
+    }
+    Run *r = find_run(s, ticket);
+    if (!r) return LGT_E_STATE;   // finishing: its result is about to arrive
+    r->cancel = true;              // admitted: stops at the next round boundary
+    lk.unlock();
+    s->cv_work.notify_one();
+    return LGT_OK;
+}
+
+lgt_status lgt_server_inject_fault(lgt_server *s, uint64_t ticket)
+{
+    if (!s) return LGT_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    Run *r = find_run(s, ticket);
+    if (!r) return LGT_E_INVALID;
+    r->inject_fault = true;
+    return LGT_OK;
+}
+
+lgt_status lgt_server_stats(lgt_server *s, lgt_server_stats_t *out)
+{
+    if (!s || !out) return LGT_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    out->budget_bytes = s->budget;
+    out->used_bytes = s->used;
+    out->pending = (int)s->pending.size();
+    out->active = (int)s->active.size();
+    out->completed = s->n_ok;
+    out->failed = s->n_failed;
+    out->cancelled = s->n_cancelled;
+    uint64_t undelivered = 0;
+    for (auto &kv : s->results) undelivered += kv.second.done ? 1 : 0;
+    out->undelivered = undelivered;
+    return LGT_OK;
 }
 
 lgt_status lgt_server_destroy(lgt_server *s)
@@ -559,6 +674,7 @@ lgt_status lgt_server_destroy(lgt_server *s)
     if (s->masks_dev) (void)hipFree(s->masks_dev);
     if (s->stage) (void)hipHostFree(s->stage);
     (void)hipStreamDestroy(s->stream);
+    for (Run *r : s->pending) delete r;   // none left: the worker cancels the queue on exit
     delete s;
     return LGT_OK;
 }

@@ -67,6 +67,13 @@ class lgt_result(ctypes.Structure):
                 ("queue_ms", ctypes.c_double)]
 
 
+class lgt_server_stats_t(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("used_bytes", ctypes.c_size_t),
+                ("pending", ctypes.c_int), ("active", ctypes.c_int),
+                ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("cancelled", ctypes.c_uint64), ("undelivered", ctypes.c_uint64)]
+
+
 # (name, restype, argtypes) of every exported entry point
 _VP = ctypes.c_void_p
 _SIGNATURES = [
@@ -107,6 +114,9 @@ _SIGNATURES = [
     ("lgt_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(lgt_result)]),
     ("lgt_server_wait", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(lgt_result)]),
     ("lgt_server_destroy", ctypes.c_int, [_VP]),
+    ("lgt_server_cancel", ctypes.c_int, [_VP, ctypes.c_uint64]),
+    ("lgt_server_stats", ctypes.c_int, [_VP, ctypes.POINTER(lgt_server_stats_t)]),
+    ("lgt_server_inject_fault", ctypes.c_int, [_VP, ctypes.c_uint64]),
 ]
 
 _lib = None
@@ -400,3 +410,17 @@ def lgt_server_wait(srv, ticket, timeout_ms=-1.0) -> lgt_result:
 
 def lgt_server_destroy(srv):
     _check(lib().lgt_server_destroy(srv))
+
+
+def lgt_server_cancel(srv, ticket):
+    _check(lib().lgt_server_cancel(srv, ticket))
+
+
+def lgt_server_stats(srv) -> dict:
+    st = lgt_server_stats_t()
+    _check(lib().lgt_server_stats(srv, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in lgt_server_stats_t._fields_}
+
+
+def lgt_server_inject_fault(srv, ticket):
+    _check(lib().lgt_server_inject_fault(srv, ticket))
