@@ -66,6 +66,10 @@ struct lgt_ctx {
     // captured launch sequences of batched evolutions, by structure (lgt_set_graphs)
     bool use_graphs = false;
     std::map<std::string, hipGraphExec_t> graphs;
+    // X density of states: a state-sized buffer and its one-step tables, made at the first
+    // LGT_OBS_XDOS and kept until lgt_destroy
+    void *xdos_buf = nullptr;
+    void *xdos_tab = nullptr;
     std::string err;
 };
 
@@ -302,11 +306,15 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
     p.pass[p.n_passes++] = Pass{PASS_TILE_LOW, 0, low, 0};
     const bool long_rows = plan != 3;
     const int rest = n_links - low, reg_max = dtype == LGT_C64 ? 6 : 5;
-    const int cb_lo = dtype == LGT_C64 ? 4 : 3;
+    // complex128 high tiles may keep rows of 64 bytes, which lets one tile rotate 11 bits
+    const int cb_lo = dtype == LGT_C64 ? 4 : 2;
     // 512-byte rows only for complex64 states beyond the 256 MB Infinity Cache, where the
     // passes stream HBM (one of the 28-link high passes runs 7-13% faster with them)
-    const int cb_hi = (dtype == LGT_C64 && n_links >= 26) ? 6 : cb_lo + 1;
-    const int nh = (rest + 9) / 10;
+    const int cb_hi = dtype == LGT_C64 ? (n_links >= 26 ? 6 : 5) : 4;
+    // most bits one high tile rotates: 10 (complex64, 128-byte rows, 16 waves), 11
+    // (complex128, 64-byte rows, 8 waves)
+    const int hmax = dtype == LGT_C64 ? 10 : 11;
+    const int nh = (rest + hmax - 1) / hmax;
     int q = low;
     for (int i = 0; i < nh; ++i) {
         const int h = rest / nh + (i < rest % nh ? 1 : 0);
@@ -560,6 +568,8 @@ lgt_status lgt_destroy(lgt_ctx *c)
     if (c->inst_dev) (void)hipFree(c->inst_dev);
     if (c->partials) (void)hipFree(c->partials);
     if (c->masks_dev) (void)hipFree(c->masks_dev);
+    if (c->xdos_buf) (void)hipFree(c->xdos_buf);
+    if (c->xdos_tab) (void)hipFree(c->xdos_tab);
     if (c->stage) (void)hipHostFree(c->stage);
     if (c->stage_free) (void)hipEventDestroy(c->stage_free);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -988,6 +998,71 @@ static lgt_status ground_circuit(lgt_ctx *c)
     return LGT_OK;
 }
 
+// The sigma^x basis of Sec. 3.3 for the X density of states: the Hadamard layer H on every
+// link, written H = S R_x(pi/2) S with S = diag(1, i).  Only |<c|H^N psi>|^2 is needed, so
+// the last S (a phase) is dropped and the transform is one fused step of the tile passes on
+// a copy of the state: the phase i^popcount(b) (the plaquette-phase slot, fed syndrome
+// tables that return b itself, so the phase index is the number of |1> links), the link
+// layer exp(-i pi/4 sigma^x) on every link (tan form t = -1, scale 2^(-N/2) in the closing
+// phase row).  The copy and its tables belong to the context from the first call on.
+static lgt_status xdos_transform(lgt_ctx *c)
+{
+    const int n = c->lat.n_links, np1 = n + 1;
+    const size_t eb = elem_bytes(c->dtype);
+    // table block: identity syndrome tables | rotation | 2 phase rows | instance
+    const size_t o_rot = sizeof(uint32_t) * kParityBytes * 256, o_ph = o_rot + 256,
+                 o_inst = align256(o_ph + 2 * np1 * eb), tab_bytes = o_inst + sizeof(DevInst);
+    if (!c->xdos_buf) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && c->state_bytes + (64u << 20) > free_b)
+            return fail(c, LGT_E_OOM, "X-DOS buffer does not fit in free device memory");
+        if (hipMalloc(&c->xdos_buf, c->state_bytes) != hipSuccess) {
+            c->xdos_buf = nullptr;
+            return fail(c, LGT_E_OOM, "X-DOS buffer");
+        }
+    }
+    if (!c->xdos_tab) {
+        std::vector<char> h(tab_bytes, 0);
+        uint32_t *id = (uint32_t *)h.data();
+        for (int k = 0; k < 4; ++k)
+            for (int v = 0; v < 256; ++v) id[k * 256 + v] = (uint32_t)v << (8 * k);
+        const double scale = std::pow(2.0, -0.5 * n);
+        static const int re4[4] = {1, 0, -1, 0}, im4[4] = {0, 1, 0, -1};
+        auto put = [&](size_t off, int i, double re, double im) {
+            if (c->dtype == LGT_C64) {
+                ((float *)(h.data() + off))[2 * i] = (float)re;
+                ((float *)(h.data() + off))[2 * i + 1] = (float)im;
+            } else {
+                ((double *)(h.data() + off))[2 * i] = re;
+                ((double *)(h.data() + off))[2 * i + 1] = im;
+            }
+        };
+        put(o_rot, 0, 1.0, -1.0);                    // (u, v) = (1, tan(-pi/4))
+        for (int m = 0; m <= n; ++m) {
+            put(o_ph, m, re4[m & 3], im4[m & 3]);     // i^m
+            put(o_ph, np1 + m, scale, 0.0);           // cos(-pi/4)^N
+        }
+        if (hipMalloc(&c->xdos_tab, tab_bytes) != hipSuccess) {
+            c->xdos_tab = nullptr;
+            return fail(c, LGT_E_OOM, "X-DOS tables");
+        }
+        DevInst di{};
+        di.psi = c->xdos_buf;
+        di.rot = (char *)c->xdos_tab + o_rot;
+        di.phase = (char *)c->xdos_tab + o_ph;
+        di.ptab = (const uint32_t *)c->xdos_tab;
+        di.n_total = 1;
+        std::memcpy(h.data() + o_inst, &di, sizeof di);
+        // written once, before any kernel reads it
+        HIPCHK(c, hipMemcpy(c->xdos_tab, h.data(), tab_bytes, hipMemcpyHostToDevice));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->xdos_buf, c->state, c->state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    const uint8_t form = kFormTan;
+    HIPCHK(c, enqueue_fused_steps(c->dtype, n, n, (const DevInst *)((char *)c->xdos_tab + o_inst), 1, 1,
+                                  0, 1, &form, c->plan, c->stream, nullptr));
+    return LGT_OK;
+}
+
 lgt_status lgt_measure(lgt_ctx *c, const lgt_observable *obs, double *out, size_t out_len)
 {
     lgt_status s = check_ctx(c);
@@ -1045,25 +1120,16 @@ lgt_status lgt_measure(lgt_ctx *c, const lgt_observable *obs, double *out, size_
         return LGT_OK;
     }
     if (obs->kind == LGT_OBS_XDOS) {
-        // sigma^x basis: Hadamard on every link of a copy, then the popcount histogram
         if (lat.n_links > kMaxPlaq) return fail(c, LGT_E_UNSUPPORTED, "X-DOS supports <= 32 links");
         if (c->n_anc) return fail(c, LGT_E_UNSUPPORTED, "X-DOS of an ancilla context");
-        void *tmp = nullptr;
-        if (hipMalloc(&tmp, c->state_bytes) != hipSuccess) return fail(c, LGT_E_OOM, "X-DOS buffer");
-        hipError_t e = hipMemcpyAsync(tmp, c->state, c->state_bytes, hipMemcpyDeviceToDevice, c->stream);
-        for (int q = 0; q < lat.n_links && e == hipSuccess; ++q)
-            e = timed(c, KF_GATE_H, [&] { return launch_gate_h(c->dtype, tmp, lat.n_links, q, c->stream); });
-        if (e == hipSuccess)
-            e = timed(c, KF_RED_DOS, [&] {
-                return launch_reduce_popcount(c->dtype, tmp, lat.n_links, c->ptab_dev, c->partials, c->stream);
-            });
+        if ((s = xdos_transform(c))) return s;
         const int g = reduce_blocks(lat.n_links);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->partials_host.data(), c->partials, sizeof(double) * g * kPartialWidth,
-                               hipMemcpyDeviceToHost, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        (void)hipFree(tmp);
-        if (e != hipSuccess) return fail(c, LGT_E_DEVICE, std::string("X-DOS: ") + hipGetErrorString(e));
+        HIPCHK(c, timed(c, KF_RED_DOS, [&] {
+            return launch_reduce_popcount(c->dtype, c->xdos_buf, lat.n_links, c->ptab_dev, c->partials, c->stream);
+        }));
+        HIPCHK(c, hipMemcpyAsync(c->partials_host.data(), c->partials, sizeof(double) * g * kPartialWidth,
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
         for (int k = 0; k <= lat.n_links; ++k) {
             long double acc = 0;
             for (int b = 0; b < g; ++b) acc += c->partials_host[(size_t)b * kPartialWidth + k];

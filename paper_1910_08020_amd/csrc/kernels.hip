@@ -1253,13 +1253,17 @@ int pass_wave_bits(int dtype, int low, int h, int cb)
 {
     // low tile of h = 10+W bits, 2 <= W <= 4 (complex64) / 3 (complex128).  High tile with
     // rows of 2^cb amplitudes rotates (6-cb) lane bits + 4 register bits + W wave bits;
-    // rows of 128, 256 or 512 bytes (complex64), 128 or 256 bytes (complex128).
+    // rows of 128, 256 or 512 bytes (complex64), 128 or 256 bytes (complex128), and for
+    // complex128 also 64-byte rows with eight waves: 11 rotated bits in 128 KiB of LDS, so
+    // that a 24-link complex128 step takes two tile passes (13 + 11 bits) instead of three
     const int wmax = dtype == LGT_C64 ? 4 : 3;
     if (low) return (h - 10 >= 2 && h - 10 <= wmax) ? h - 10 : -1;
-    const int cb_lo = dtype == LGT_C64 ? 4 : 3, cb_hi = dtype == LGT_C64 ? 6 : 4;
+    const int cb_lo = dtype == LGT_C64 ? 4 : 2, cb_hi = dtype == LGT_C64 ? 6 : 4;
     if (cb < cb_lo || cb > cb_hi) return -1;
     const int w = h - (10 - cb);
-    return (w < 0 || w > wmax) ? -1 : w;
+    if (w < 0 || w > wmax) return -1;
+    if (dtype != LGT_C64 && cb == 2 && w != 3) return -1;
+    return w;
 }
 
 bool pass_offsets_fit(int dtype, int n, int low, int hb, int h, int cb)
@@ -1308,7 +1312,9 @@ hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, in
         if (w == 2) return launch_pass_t<double, 2, 12>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, merge, st);
         return launch_pass_t<double, 3, 13>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, merge, st);
     }
-    if (cb == 3) {
+    if (cb == 2) {
+        if (w == 3) return launch_pass_t<double, 3, 2>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st);
+    } else if (cb == 3) {
         LGT_PASS_CASES(double, 3)
     } else {
         LGT_PASS_CASES(double, 4)

@@ -15,4 +15,4 @@ def test_every_tile_geometry(tmp_path):
     lines = r.stdout.strip().splitlines()
     assert r.returncode == 0, r.stdout
     assert lines[-1] == "failures: 0"
-    assert sum(1 for ln in lines if ln.endswith(": ok")) == 28
+    assert sum(1 for ln in lines if ln.endswith(": ok")) == 29
