@@ -1,17 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: Trotterized adiabatic Z2 lattice-gauge evolution on one MI355X.
 
-One benchmark step is one complete run of the 2x2x2 (24-link) 3+1D workload:
-for each coupling lambda in {0.2, 0.5, 1.0, 2.0}, prepare |+>^24, apply 2000
-symmetric Trotter steps (T = 100, H(s) = -lambda sum sigma^x - s sum U_p,
-s ramping to 1) on the GPU in complex64, and read out the energy, every
-plaquette, the Wilson loops and the Gauss-law stars in FP64.
+One benchmark step is one complete run of the 2x2x2 (24-link) 3+1D workload in the
+paper's arithmetic (FP64: complex128 amplitudes): for each coupling lambda in
+{0.2, 0.5, 1.0, 2.0}, prepare |+>^24, apply 2000 symmetric Trotter steps (T = 100,
+H(s) = -lambda sum sigma^x - s sum U_p, s ramping to 1), and read out in FP64 the energy,
+every plaquette and link, the Wilson contours c1..c3 and lines, and the Gauss-law stars.
 
-The printed JSON line carries amp-updates/s (2^N (N_l + 1) amplitude updates
-per Trotter step), the roofline record of the dominant kernel (HIP-event
-timed inside the timed region), the oracle timed on the host cores, and the
-secondary metrics: the batched 3x3 lambda scan against the per-instance path
-and a continuous-batching serving run (p50/p99 latency, solves/s).
+The printed JSON line carries amp-updates/s (2^N (N_l + 1) amplitude updates per Trotter
+step), the roofline record of the dominant kernel (HIP-event timed inside the timed region),
+the errors of the readout against the stored FP64 oracle runs, the oracle timed on the host
+cores, and secondary records: the same workload in complex64 (with per-result errors), the
+HBM-streaming 32-link passes, the 4x4 runs against the dual oracle, batched lambda scans
+against the per-instance path, a continuous-batching serving run (p50/p99 latency,
+solves/s), bandwidth sweeps and the paper's own scans.
 """
 from __future__ import annotations
 
@@ -32,6 +34,7 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+INFINITY_CACHE_BYTES = 256 << 20
 
 
 def _lgt():
@@ -54,7 +57,7 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
-def run_job(lgt, ctx, w, masks, stars_n, plaq_n):
+def run_job(lgt, ctx, w, masks, stars_n, plaq_n, links_n):
     """One complete workload run: every lambda, full schedule, FP64 readout."""
     out = []
     for lam in w.lambdas:
@@ -63,12 +66,23 @@ def run_job(lgt, ctx, w, masks, stars_n, plaq_n):
         lgt.lgt_evolve(ctx, s, w.order, lgt.LGT_FORM_FUSED, 0, w.n_steps)
         e = lgt.lgt_measure(ctx, lgt.LGT_OBS_ENERGY, cx=lam, cz=1.0)[0]
         plaq = lgt.lgt_measure(ctx, lgt.LGT_OBS_PLAQ)[:plaq_n]
+        sx = lgt.lgt_measure(ctx, lgt.LGT_OBS_SIGMAX)[:links_n]
         wl = lgt.lgt_measure(ctx, lgt.LGT_OBS_Z, masks=masks)[: len(masks)]
         st = lgt.lgt_measure(ctx, lgt.LGT_OBS_STAR)[:stars_n]
         out.append({"lambda": lam, "energy": float(e), "plaq_mean": float(np.mean(plaq)),
-                    "wilson": [float(x) for x in wl],
+                    "plaq": [float(x) for x in plaq], "sigma_x": [float(x) for x in sx],
+                    "wilson": [float(x) for x in wl], "stars": [float(x) for x in st],
                     "gauss_violation": float(np.max(np.abs(1 - st)))})
     return out
+
+
+def cache_residency(state_bytes: int) -> str:
+    """Where a state lives between passes: MI355X has a 256 MiB Infinity Cache in front of HBM."""
+    if state_bytes < INFINITY_CACHE_BYTES:
+        return "resident in the Infinity Cache"
+    if state_bytes == INFINITY_CACHE_BYTES:
+        return "the size of the Infinity Cache (partly resident)"
+    return "streams HBM"
 
 
 def roofline_from_stats(stats, state_bytes, traffic):
@@ -85,12 +99,13 @@ def roofline_from_stats(stats, state_bytes, traffic):
     return {"bound": "hbm", "kernel": name, "launches": int(launches),
             "avg_us": avg_s * 1e6, "bytes_per_launch": algo,
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "state_bytes": state_bytes, "state_in_memory": cache_residency(state_bytes)}
 
 
-def load_traffic(kernel_name):
+def load_traffic(key):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel sources."""
+    taken on the current kernel sources.  key: "<dtype>:<torus>:<family>"."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -100,16 +115,193 @@ def load_traffic(kernel_name):
         return None
     if d.get("source_hash") != kernel_source_hash():
         return None
-    k = d.get("kernels", {}).get(kernel_name)
+    k = d.get("kernels", {}).get(key)
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def lambda_scan(lgt, steps=None):
-    """3x3, 21 couplings, symmetric, complex64: one batched launch sequence versus
-    21 sequential per-instance runs on the same GPU."""
+def timed_workload(lgt, w, dtype, steps, warmup, stride):
+    """The benchmark step (every lambda of the workload, full schedule, FP64 readout) run
+    `warmup` times untimed and `steps` times timed, the pass kernels bracketed with HIP events
+    (every `stride`-th launch of each kernel family) inside the timed region."""
+    ctx = lgt.lgt_create(w.d, list(w.L), 1, dtype)
+    try:
+        info = lgt.lgt_info(ctx)
+        n_links, n_plaq, n_sites = info["n_links"], info["n_plaq"], info["n_sites"]
+        masks = [lgt.lgt_contour_mask(ctx, k) for k in (1, 2, 3)] + \
+                [lgt.lgt_line_mask(ctx, 0, mu) for mu in range(w.d)]
+        for _ in range(warmup):
+            run_job(lgt, ctx, w, masks, n_sites, n_plaq, n_links)
+        lgt.lgt_sync(ctx)
+        lgt.lgt_set_profiling(ctx, max(1, stride))
+        lgt.lgt_sync(ctx)
+        t0 = time.perf_counter()
+        results = None
+        for _ in range(steps):
+            results = run_job(lgt, ctx, w, masks, n_sites, n_plaq, n_links)
+        lgt.lgt_sync(ctx)
+        elapsed = time.perf_counter() - t0
+        stats = lgt.lgt_kernel_stats(ctx)
+        lgt.lgt_set_profiling(ctx, False)
+        plan = lgt.lgt_plan_describe(ctx)
+        state_bytes = info["state_bytes"]
+    finally:
+        lgt.lgt_destroy(ctx)
+    upd = steps * len(w.lambdas) * w.n_steps * (1 << n_links) * (n_links + 1)
+    trotter_steps = steps * len(w.lambdas) * w.n_steps
+    name = "c64" if dtype == lgt.LGT_C64 else "c128"
+    roof = roofline_from_stats(stats, state_bytes, None)
+    if roof:
+        roof["traffic"] = load_traffic(f"{name}:{'x'.join(map(str, w.L))}:{roof['kernel']}")
+    return {"value": upd / elapsed, "elapsed": elapsed, "plan": plan,
+            "us_per_trotter_step": elapsed / trotter_steps * 1e6,
+            "algorithmic_hbm_frac_per_trotter_step":
+                (2 * state_bytes / (HBM_PEAK_GBS * 1e9)) / (elapsed / trotter_steps),
+            "kernel_stats_ms": {k: [int(v[0]), v[1]] for k, v in stats.items()},
+            "roofline": roof, "readout": results, "state_bytes": state_bytes,
+            "masks": {"contours_c1_c2_c3": [int(m) for m in masks[:3]],
+                      "lines": [int(m) for m in masks[3:]]}}
+
+
+def _golden(name):
+    """Stored oracle values (tests/golden, written by make_golden.py from the oracle only)."""
+    p = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        return json.load(fh)
+
+
+def errors_against_oracle(readout, w):
+    """Per coupling: the largest error of every observable against the stored oracle run."""
+    out = []
+    for r in readout:
+        g = _golden(f"config3_full_lam{r['lambda']}.json")
+        if g is None:
+            out.append({"lambda": r["lambda"], "oracle": "not stored"})
+            continue
+        out.append({"lambda": r["lambda"],
+                    "energy_err": abs(r["energy"] - g["energy"]),
+                    "plaq_err_max": float(np.max(np.abs(np.subtract(r["plaq"], g["plaq"])))),
+                    "sigma_x_err_max": float(np.max(np.abs(np.subtract(r["sigma_x"], g["sigma_x"])))),
+                    "stars_err_max": float(np.max(np.abs(np.subtract(r["stars"], g["stars"])))),
+                    "wilson_lines_err_max": float(np.max(np.abs(np.subtract(
+                        r["wilson"][3:], g["wilson_lines"]["values"]))))})
+    return out
+
+
+def complex64_line(lgt, w, ref128, stride):
+    """The same workload with complex64 amplitudes (FP32 tables, FP64 readout): throughput,
+    roofline, and per coupling the error of every observable against the stored FP64 oracle
+    run and the state infidelity against the complex128 GPU path (itself within 1e-10 of the
+    oracle in the parity tests)."""
+    r = timed_workload(lgt, w, lgt.LGT_C64, 1, 1, stride)
+    errs = errors_against_oracle(r["readout"], w)
+    # infidelity per coupling: both precisions rerun to the end, states compared on the host
+    infid = []
+    c64 = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64)
+    c128 = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C128)
+    try:
+        i64, i128 = lgt.lgt_info(c64), lgt.lgt_info(c128)
+        for lam in w.lambdas:
+            s = lgt.make_schedule(w.T, w.n_steps, lam, 1.0)
+            for c in (c64, c128):
+                lgt.lgt_reset(c, lgt.LGT_INIT_PLUS, 0)
+                lgt.lgt_evolve(c, s, w.order, lgt.LGT_FORM_FUSED, 0, w.n_steps)
+            a = lgt.lgt_get_state(c64, i64["state_bytes"], np.complex64).astype(np.complex128)
+            b = lgt.lgt_get_state(c128, i128["state_bytes"], np.complex128)
+            na, nb = np.vdot(a, a).real, np.vdot(b, b).real
+            infid.append({"lambda": lam, "infidelity_vs_c128": float(1 - abs(np.vdot(a, b)) ** 2 / (na * nb)),
+                          "norm_c64_minus_1": float(na - 1)})
+    finally:
+        lgt.lgt_destroy(c64)
+        lgt.lgt_destroy(c128)
+    for e, f, a, b in zip(errs, infid, r["readout"], ref128):
+        e.update(f)
+        e["energy_err_vs_c128"] = abs(a["energy"] - b["energy"])
+    return {"metric": "amp-updates/s", "value": r["value"], "dtype": "c64",
+            "us_per_trotter_step": r["us_per_trotter_step"], "plan": r["plan"],
+            "algorithmic_hbm_frac_per_trotter_step": r["algorithmic_hbm_frac_per_trotter_step"],
+            "roofline": r["roofline"], "kernel_stats_ms": r["kernel_stats_ms"],
+            "errors_per_result": errs}
+
+
+def hbm_rooflines(lgt, steps=6):
+    """32 links (4x4): 32 GiB (complex64) and 64 GiB (complex128) states stream HBM on every
+    pass.  Every pass kernel launch is timed with HIP events on its own dispatch; each family's
+    mean gives achieved bytes (one read + one write of the state) per launch against 8 TB/s,
+    and the Trotter step time gives the algorithmic fraction (one read + one write per
+    step)."""
+    out = {}
+    for name, dtype in (("c64", lgt.LGT_C64), ("c128", lgt.LGT_C128)):
+        ctx = lgt.lgt_create(2, [4, 4], 1, dtype)
+        try:
+            sb = lgt.lgt_info(ctx)["state_bytes"]
+            s = lgt.make_schedule(0.05 * 1000, 1000, 1.0, 1.0)
+            lgt.lgt_evolve(ctx, s, lgt.LGT_ORDER_SYMMETRIC, lgt.LGT_FORM_FUSED, 0, 2)
+            lgt.lgt_sync(ctx)
+            lgt.lgt_set_profiling(ctx, 1)
+            t0 = time.perf_counter()
+            lgt.lgt_evolve(ctx, s, lgt.LGT_ORDER_SYMMETRIC, lgt.LGT_FORM_FUSED, 2, steps)
+            lgt.lgt_sync(ctx)
+            el = time.perf_counter() - t0
+            stats = lgt.lgt_kernel_stats(ctx)
+            lgt.lgt_set_profiling(ctx, False)
+            plan = lgt.lgt_plan_describe(ctx)
+        finally:
+            lgt.lgt_destroy(ctx)
+        fam = {}
+        for k, (n, ms) in stats.items():
+            if k.startswith("tile") or k.startswith("pass"):
+                avg = ms / n / 1e3
+                fam[k] = {"launches": int(n), "avg_ms": avg * 1e3,
+                          "achieved_GBps": 2 * sb / avg / 1e9,
+                          "frac": 2 * sb / avg / 1e9 / HBM_PEAK_GBS}
+        out[f"4x4_{name}"] = {"state_bytes": sb, "plan": plan, "steps": steps,
+                              "ms_per_trotter_step": el / steps * 1e3,
+                              "algorithmic_frac_per_trotter_step": 2 * sb / (el / steps) / 1e9 / HBM_PEAK_GBS,
+                              "pass_families": fam}
+    return out
+
+
+def config5_runs(lgt):
+    """4x4 (32 links, 32 GiB complex64), 1000 symmetric steps, T = 50, lambda in
+    {0.5, 1.0, 1.5}: per coupling the time per Trotter step and every <U_p> and <sigma^x_l>
+    against the stored exact Wegner-dual oracle values, the Gauss law and the norm."""
+    w = workloads.CONFIG5
+    gold = _golden("config5_dual.json")
+    out = []
+    ctx = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64)
+    try:
+        info = lgt.lgt_info(ctx)
+        for lam in w.lambdas:
+            lgt.lgt_reset(ctx, lgt.LGT_INIT_PLUS, 0)
+            lgt.lgt_sync(ctx)
+            t0 = time.perf_counter()
+            lgt.lgt_evolve(ctx, lgt.make_schedule(w.T, w.n_steps, lam, 1.0), w.order)
+            lgt.lgt_sync(ctx)
+            el = time.perf_counter() - t0
+            up = lgt.lgt_measure(ctx, lgt.LGT_OBS_PLAQ)[: info["n_plaq"]]
+            sx = lgt.lgt_measure(ctx, lgt.LGT_OBS_SIGMAX)[: info["n_links"]]
+            st = lgt.lgt_measure(ctx, lgt.LGT_OBS_STAR)[: info["n_sites"]]
+            nrm = lgt.lgt_measure(ctx, lgt.LGT_OBS_NORM)[0]
+            r = {"lambda": lam, "ms_per_trotter_step": el / w.n_steps * 1e3,
+                 "gauss_violation": float(np.max(np.abs(1 - st))), "norm_minus_1": float(nrm - 1)}
+            g = gold["results"].get(repr(lam)) if gold else None
+            if g:
+                r["plaq_err_max_vs_dual_oracle"] = float(np.max(np.abs(up - g["plaq"])))
+                r["sigma_x_err_max_vs_dual_oracle"] = float(np.max(np.abs(sx - g["sigma_x"])))
+            out.append(r)
+    finally:
+        lgt.lgt_destroy(ctx)
+    return {"workload": w.name + ", complex64", "results": out}
+
+
+def lambda_scan(lgt, dtype, steps=None):
+    """3x3, 21 couplings, symmetric: one batched launch sequence versus 21 sequential
+    per-instance runs on the same GPU."""
     w = workloads.CONFIG2
     n = steps or w.n_steps
-    ctxs = [lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64) for _ in w.lambdas]
+    ctxs = [lgt.lgt_create(w.d, list(w.L), 1, dtype) for _ in w.lambdas]
     try:
         scheds = [lgt.make_schedule(w.T * n / w.n_steps, n, lam, 1.0) for lam in w.lambdas]
         orders = [w.order] * len(ctxs)
@@ -137,7 +329,8 @@ def lambda_scan(lgt, steps=None):
         for c in ctxs:
             lgt.lgt_destroy(c)
     k = len(w.lambdas)
-    return {"workload": f"3x3 (18 links), {k} lambdas, {n} symmetric steps, complex64",
+    name = "complex64" if dtype == lgt.LGT_C64 else "complex128"
+    return {"workload": f"3x3 (18 links), {k} lambdas, {n} symmetric steps, {name}",
             "batched_solves_per_s": k / t_batch, "per_instance_solves_per_s": k / t_single,
             "speedup": t_single / t_batch, "batched_s": t_batch, "per_instance_s": t_single}
 
@@ -163,13 +356,19 @@ def serving(lgt, n_requests, rate):
             tickets.append(lgt.lgt_server_submit(srv, q))
         res = [lgt.lgt_server_wait(srv, t, 600000.0) for t in tickets]
         wall = time.perf_counter() - t0
+        stats = lgt.lgt_server_stats(srv)
     finally:
         lgt.lgt_server_destroy(srv)
     lat = np.array([r.latency_ms for r in res])
+    queue = np.array([r.queue_ms for r in res])
     ok = sum(1 for r in res if r.status == lgt.LGT_OK)
     return {"requests": n_requests, "offered_rate_per_s": rate, "completed_ok": ok,
             "solves_per_s": ok / wall, "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "wall_s": wall,
+            "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
+            "queue_p50_ms": float(np.percentile(queue, 50)),
+            "queue_p99_ms": float(np.percentile(queue, 99)), "wall_s": wall,
+            "max_gauss_violation": float(max(r.gauss_violation for r in res)),
+            "server_counters": {k: int(v) for k, v in stats.items()},
             "mix": "60% 3x3, 30% 2x2x2, 10% 2x2; lambda U[0,2]; steps U{500..4000}; order 1|2"}
 
 
@@ -235,93 +434,122 @@ def _oracle_single_thread(target_s=4.0) -> dict | None:
             "sample": f"{done} symmetric Trotter steps of the same run, {el:.1f} s"}
 
 
-def paper_scans(lgt):
-    """The paper's own workload (Sec. 2.2, 2.6, 3.2): H = Z + g X, g from 0 to 2 in 2000 steps
-    of 0.001, each step n substeps, from the projected Z ground state, measured after every
-    step; g_c from the lowest point of d2<H>/dg2 and the <Z> = <X> crossing."""
+def _wilson_ratios(rows, g_points):
+    """log<W_c2>/log<W_c1> and log<W_c3>/log<W_c1> (Sec. 3.1: perimeter ratios 1.5 and 2 in
+    the deconfined phase, area ratios 2 and 3 in the confined one) at the given couplings;
+    rows carry <W_c1..c3> in columns 5..7."""
+    g = rows[:, 0]
     out = {}
-    for name, (d, L, order, n, t_s) in {
-            "2x2x2_symmetric_n200_ts0.1": (3, (2, 2, 2), 2, 200, 0.1),
-            "3x3_first_order_n500_ts0.02": (2, (3, 3), 1, 500, 0.02)}.items():
-        ctx = lgt.lgt_create(d, list(L), 1, lgt.LGT_C64)
-        try:
-            lgt.lgt_reset(ctx, lgt.LGT_INIT_ZGROUND, 0)
-            s = lgt.make_schedule(t_s * 2000, n * 2000, ramp=lgt.LGT_RAMP_COUPLING, g0=0.0, g1=2.0)
-            t0 = time.perf_counter()
-            rows = lgt.lgt_scan(ctx, s, order, 0, n, 2000)
-            el = time.perf_counter() - t0
-        finally:
-            lgt.lgt_destroy(ctx)
+    for gq in g_points:
+        i = int(np.argmin(np.abs(g - gq)))
+        w1, w2, w3 = rows[i, 5:8]
+        out[f"{g[i]:.3f}"] = {"W_c1_c2_c3": [float(w1), float(w2), float(w3)],
+                              "ratio_c2_c1": float(np.log(w2) / np.log(w1)),
+                              "ratio_c3_c1": float(np.log(w3) / np.log(w1))}
+    return out
+
+
+def _scan(lgt, d, L, order, n, t_s, n_steps=2000, g_f=2.0, signs=None, masks=True):
+    """The paper's stepwise scan (Sec. 2.2, 2.6): g from 0 to g_f in n_steps steps of
+    n substeps of t_s / n, from the projected Z ground state (moved to another topological
+    sector by Wilson lines when `signs` says so), measured after every step, complex64."""
+    ctx = lgt.lgt_create(d, list(L), 1, lgt.LGT_C64)
+    try:
+        lgt.lgt_reset(ctx, lgt.LGT_INIT_ZGROUND, 0)
+        for mu, sgn in enumerate(signs or ()):
+            if sgn < 0:
+                lgt.lgt_apply_pauli(ctx, 0, lgt.lgt_line_mask(ctx, 0, mu))
+        mk = [lgt.lgt_contour_mask(ctx, k) for k in (1, 2, 3)] if masks else None
+        s = lgt.make_schedule(t_s * n_steps, n * n_steps, ramp=lgt.LGT_RAMP_COUPLING, g0=0.0,
+                              g1=g_f)
+        t0 = time.perf_counter()
+        rows = lgt.lgt_scan(ctx, s, order, 0, n, n_steps, mk)
+        return rows, time.perf_counter() - t0
+    finally:
+        lgt.lgt_destroy(ctx)
+
+
+def paper_scans(lgt):
+    """The paper's own workload (Sec. 2.2, 2.6, 3.1, 3.2, 3.5): H = Z + g X, g from 0 to 2 in
+    2000 steps of 0.001, each step n substeps, from the projected Z ground state, measured
+    after every step: g_c from the lowest point of d2<H>/dg2, the <Z> = <X> crossing, the
+    Wilson contours c1..c3 and their log ratios, and the topological-sector splittings."""
+    import concurrent.futures as cf
+    out = {}
+    runs = {"2x2x2_symmetric_n200_ts0.1": (3, (2, 2, 2), 2, 200, 0.1),
+            "3x3_symmetric_n5000_ts0.2": (2, (3, 3), 2, 5000, 0.2),
+            "3x3_first_order_n500_ts0.02": (2, (3, 3), 1, 500, 0.02)}
+    for name, (d, L, order, n, t_s) in runs.items():
+        rows, el = _scan(lgt, d, L, order, n, t_s)
         g, z, x = rows[:, 0], rows[:, 2], rows[:, 3]
         r = {"substeps": n * 2000, "measurements": 2000, "seconds": el,
              "us_per_substep_incl_measurement": el / (n * 2000) * 1e6,
              "g_c_d2H_min": lgt.lgt_critical_point(g, z + g * x, stride=10)[0],
              "Z_at_g0.001": float(z[0]), "X_at_g2": float(x[-1]),
-             "max_norm_drift": float(np.max(np.abs(rows[:, 4] - 1)))}
+             "max_norm_drift": float(np.max(np.abs(rows[:, 4] - 1))),
+             "wilson_log_ratios": _wilson_ratios(rows, (0.05, 0.1, 0.3, 0.5, 1.0, 2.0))}
         try:
             r["Z_X_crossing"] = lgt.lgt_crossing(g, z, x)
         except lgt.LgtError:
             r["Z_X_crossing"] = None
-        r["Z(g)-X(1/g) at g=0.5,0.8"] = [float(z[499] - x[1999]), float(z[799] - x[1249])]
+        if d == 3:
+            r["Z(g)-X(1/g) at g=0.5,0.8"] = [float(z[499] - x[1999]), float(z[799] - x[1249])]
         out[name] = r
-    # Sec. 3.5: the four topological sectors of 3x3, splittings E_i1^(1/4) linear in g
-    E = {}
+    # Sec. 3.5: the four topological sectors of 3x3 on the paper's symmetric schedule
+    # (n = 5000, t_s = 0.2) up to g = 0.5, the four runs side by side on their own streams;
+    # splittings E_i1^(1/4) linear in g
+    signs_all = [(1, 1), (-1, 1), (1, -1), (-1, -1)]
     t0 = time.perf_counter()
-    for signs in [(1, 1), (-1, 1), (1, -1), (-1, -1)]:
-        ctx = lgt.lgt_create(2, [3, 3], 1, lgt.LGT_C64)
-        try:
-            lgt.lgt_reset(ctx, lgt.LGT_INIT_ZGROUND, 0)
-            for mu, sgn in enumerate(signs):
-                if sgn < 0:
-                    lgt.lgt_apply_pauli(ctx, 0, lgt.lgt_line_mask(ctx, 0, mu))
-            s = lgt.make_schedule(0.02 * 500, 500 * 500, ramp=lgt.LGT_RAMP_COUPLING, g0=0.0, g1=0.5)
-            rows = lgt.lgt_scan(ctx, s, 1, 0, 500, 500)
-        finally:
-            lgt.lgt_destroy(ctx)
-        E[signs] = rows[:, 2] + rows[:, 0] * rows[:, 3]
-        g = rows[:, 0]
+    with cf.ThreadPoolExecutor(4) as ex:
+        res = list(ex.map(lambda sg: _scan(lgt, 2, (3, 3), 2, 5000, 0.2, n_steps=500, g_f=0.5,
+                                           signs=sg, masks=False)[0], signs_all))
+    E = {sg: r[:, 2] + r[:, 0] * r[:, 3] for sg, r in zip(signs_all, res)}
+    g = res[0][:, 0]
     sl = slice(49, 300)
     fits = {}
     for name, key in (("E21", (-1, 1)), ("E31", (1, -1)), ("E41", (-1, -1))):
         a, b = np.polyfit(g[sl], np.abs(E[key] - E[(1, 1)])[sl] ** 0.25, 1)
         fits[name] = {"slope": float(a), "intercept": float(b)}
-    out["3x3_sectors_first_order_to_g0.5"] = {
+    out["3x3_sectors_symmetric_n5000_ts0.2_to_g0.5"] = {
         "seconds": time.perf_counter() - t0, "fit_window_g": [0.05, 0.30],
         "fits_E_i1^(1/4)=a*g+b": fits,
         "paper": {"E21": [1.88719, 0.02516], "E41": [2.08307, 0.0441229]}}
-    out["paper_values"] = {"g_c_2x2x2": 0.986, "g_c_3x3": 0.380, "crossing_2x2x2": 1.0}
+    out["paper_values"] = {"g_c_2x2x2": 0.986, "g_c_3x3": 0.380, "crossing_2x2x2": 1.0,
+                           "wilson_ratios": "perimeter 1 : 1.5 : 2, area 1 : 2 : 3"}
     return out
 
 
-def bandwidth_sweep(lgt, steps=50, reps=5):
-    """Complex64 tori from 24 to 32 links, symmetric steps: median time per Trotter step over
-    `reps` calls of `steps` steps, the bytes the plan moves (one read and one write of the
-    state per launch) and the algorithmic two passes' worth, each against 8 TB/s."""
+def bandwidth_sweep(lgt, dtype, steps=50, reps=5):
+    """Tori from 24 to 32 links, symmetric steps: median time per Trotter step over `reps`
+    calls of `steps` steps (fewer for states over 16 GiB), the bytes the plan moves (one read
+    and one write of the state per launch) and the algorithmic two passes' worth, each
+    against 8 TB/s."""
     out = {}
     for d, L in ((2, (3, 4)), (3, (2, 2, 2)), (2, (2, 7)), (2, (3, 5)), (2, (4, 4))):
-        ctx = lgt.lgt_create(d, list(L), 1, lgt.LGT_C64)
+        ctx = lgt.lgt_create(d, list(L), 1, dtype)
         try:
             info = lgt.lgt_info(ctx)
             sb = info["state_bytes"]
+            nst, nrep = (steps, reps) if sb <= (16 << 30) else (max(4, steps // 8), 3)
             desc = lgt.lgt_plan_describe(ctx)
             n_pass = desc.split(";")[0].count("|") + 1
             merged = "steps merged" in desc
-            launches = steps * (n_pass - 1) + 1 if merged else steps * n_pass
-            s = lgt.make_schedule(0.05 * steps, steps, 1.0, 1.0)
+            launches = nst * (n_pass - 1) + 1 if merged else nst * n_pass
+            s = lgt.make_schedule(0.05 * nst, nst, 1.0, 1.0)
             lgt.lgt_evolve(ctx, s, lgt.LGT_ORDER_SYMMETRIC, lgt.LGT_FORM_FUSED, 0, 4)
             lgt.lgt_sync(ctx)
             ts = []
-            for _ in range(reps):
+            for _ in range(nrep):
                 t0 = time.perf_counter()
-                lgt.lgt_evolve(ctx, s, lgt.LGT_ORDER_SYMMETRIC, lgt.LGT_FORM_FUSED, 0, steps)
+                lgt.lgt_evolve(ctx, s, lgt.LGT_ORDER_SYMMETRIC, lgt.LGT_FORM_FUSED, 0, nst)
                 lgt.lgt_sync(ctx)
                 ts.append(time.perf_counter() - t0)
-            t = float(np.median(ts)) / steps
+            t = float(np.median(ts)) / nst
         finally:
             lgt.lgt_destroy(ctx)
-        moved = launches / steps * 2 * sb
+        moved = launches / nst * 2 * sb
         out["x".join(map(str, L))] = {
-            "links": info["n_links"], "plan": desc, "launches_per_step": launches / steps,
+            "links": info["n_links"], "plan": desc, "launches_per_step": launches / nst,
             "us_per_step": t * 1e6, "implementation_GBps": moved / t / 1e9,
             "implementation_hbm_frac": moved / t / 1e9 / HBM_PEAK_GBS,
             "algorithmic_hbm_frac": 2 * sb / t / 1e9 / HBM_PEAK_GBS}
@@ -358,6 +586,11 @@ def variants(lgt):
     # 28 links (2 GiB): larger than the 256 MB Infinity Cache, so the passes stream HBM
     out["2x7_c64_fused_28links"] = per_step(2, (2, 7), lgt.LGT_C64, 40)
     out["2x2x2_c128_fused"] = per_step(3, (2, 2, 2), lgt.LGT_C128, 200)
+    # complex128 on the three-pass plan of 12-bit low tiles (the one-launch-per-step plan
+    # needs the 11-bit high tile with 64-byte rows)
+    out["2x2x2_c128_fused_low12_three_passes"] = per_step(3, (2, 2, 2), lgt.LGT_C128, 200, plan=1)
+    out["2x2x2_c128_fused_unmerged"] = per_step(3, (2, 2, 2), lgt.LGT_C128, 200,
+                                                plan=lgt.LGT_PLAN_NO_MERGE)
     out["2x2x2_c64_circuit"] = per_step(3, (2, 2, 2), lgt.LGT_C64, 4, form=1)
     out["2x2x2_c128_circuit"] = per_step(3, (2, 2, 2), lgt.LGT_C128, 2, form=1)
     # eq. (ara) with the ancilla (25 qubits), and its time-direction-controlled variant
@@ -409,44 +642,6 @@ def phase_estimation(lgt):
             "seconds": el}
 
 
-def precision(lgt):
-    """Per coupling of the benchmark workload: the complex64 result against the complex128
-    GPU path (itself held to the FP64 oracle at 1e-10 by the parity tests): state
-    infidelity, energy and plaquette errors, and each path's Gauss-law violation."""
-    w = workloads.CONFIG3
-    out = []
-    ctx64 = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64)
-    ctx128 = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C128)
-    try:
-        i64, i128 = lgt.lgt_info(ctx64), lgt.lgt_info(ctx128)
-        n_plaq, n_sites = i64["n_plaq"], i64["n_sites"]
-        for lam in w.lambdas:
-            res = {}
-            for name, ctx in (("c64", ctx64), ("c128", ctx128)):
-                lgt.lgt_reset(ctx, lgt.LGT_INIT_PLUS, 0)
-                s = lgt.make_schedule(w.T, w.n_steps, lam, 1.0)
-                lgt.lgt_evolve(ctx, s, w.order, lgt.LGT_FORM_FUSED, 0, w.n_steps)
-                res[name] = {
-                    "energy": lgt.lgt_measure(ctx, lgt.LGT_OBS_ENERGY, cx=lam, cz=1.0)[0],
-                    "plaq": lgt.lgt_measure(ctx, lgt.LGT_OBS_PLAQ)[:n_plaq],
-                    "stars": lgt.lgt_measure(ctx, lgt.LGT_OBS_STAR)[:n_sites],
-                    "norm": lgt.lgt_measure(ctx, lgt.LGT_OBS_NORM)[0]}
-            a = lgt.lgt_get_state(ctx64, i64["state_bytes"], np.complex64).astype(np.complex128)
-            b = lgt.lgt_get_state(ctx128, i128["state_bytes"], np.complex128)
-            fid = abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
-            out.append({"lambda": lam, "infidelity_c64_vs_c128": float(1 - fid),
-                        "energy_err": float(abs(res["c64"]["energy"] - res["c128"]["energy"])),
-                        "plaq_err_max": float(np.max(np.abs(res["c64"]["plaq"] - res["c128"]["plaq"]))),
-                        "norm_c64": float(res["c64"]["norm"]),
-                        "gauss_violation_c64": float(np.max(np.abs(1 - res["c64"]["stars"]))),
-                        "gauss_violation_c128": float(np.max(np.abs(1 - res["c128"]["stars"]))),
-                        "energy_c128": float(res["c128"]["energy"])})
-    finally:
-        lgt.lgt_destroy(ctx64)
-        lgt.lgt_destroy(ctx128)
-    return out
-
-
 def long_run_precision(lgt, n=200_000, dt=4e-5):
     """Complex64 against complex128 over the paper's kind of run (Sec. 2.2, 2.6): 3x3 from
     the projected Z ground state, 2 x 10^5 substeps of t_s/n = 4e-5, the coupling ramped
@@ -487,14 +682,16 @@ def main():
     ap.add_argument("--event-stride", type=int, default=8,
                     help="bracket every k-th launch of each kernel family with HIP events "
                          "in the timed region (1 = every launch)")
-    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--profile-steps", type=int, default=0,
-                    help="profiling runs only: Trotter steps per lambda instead of the full "
-                         "schedule, plus one device-to-device copy of the state (a copy of "
-                         "known size for counter calibration); prints no benchmark line")
+                    help="profiling runs only: Trotter steps of the first coupling instead of "
+                         "the benchmark, plus one device-to-device copy of the state (a copy "
+                         "of known size for counter calibration); prints no benchmark line")
     ap.add_argument("--profile-lattice", default="2x2x2",
-                    help="profiling runs only: the torus, e.g. 2x7 or 4x4 (complex64)")
+                    help="profiling runs only: the torus, e.g. 2x7 or 4x4")
+    ap.add_argument("--profile-dtype", default="c128", choices=("c64", "c128"),
+                    help="profiling runs only: the amplitude type")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs one state per GPU; only --gpus 1 is "
@@ -505,75 +702,72 @@ def main():
     w = workloads.CONFIG3
     if args.profile_steps > 0:
         L = [int(x) for x in args.profile_lattice.split("x")]
-        ctx = lgt.lgt_create(len(L), L, 1, lgt.LGT_C64)
+        dt = lgt.LGT_C64 if args.profile_dtype == "c64" else lgt.LGT_C128
+        ctx = lgt.lgt_create(len(L), L, 1, dt)
         info = lgt.lgt_info(ctx)
-        other = lgt.lgt_create(len(L), L, 1, lgt.LGT_C64)
-        for lam in w.lambdas[:1]:
-            s = lgt.make_schedule(w.T, w.n_steps, lam, 1.0)
-            lgt.lgt_evolve(ctx, s, w.order, lgt.LGT_FORM_FUSED, 0, args.profile_steps)
+        other = lgt.lgt_create(len(L), L, 1, dt)
+        s = lgt.make_schedule(w.T, w.n_steps, w.lambdas[0], 1.0)
+        lgt.lgt_evolve(ctx, s, w.order, lgt.LGT_FORM_FUSED, 0, args.profile_steps)
         lgt.lgt_copy_state(other, ctx)
         lgt.lgt_sync(other)
         print(json.dumps({"profile_steps": args.profile_steps, "lattice": args.profile_lattice,
+                          "dtype": args.profile_dtype, "plan": lgt.lgt_plan_describe(ctx),
                           "copy_bytes": info["state_bytes"]}), flush=True)
         lgt.lgt_destroy(other)
         lgt.lgt_destroy(ctx)
         return
-    ctx = lgt.lgt_create(w.d, list(w.L), 1, lgt.LGT_C64)
-    info = lgt.lgt_info(ctx)
-    n_links, n_plaq, n_sites = info["n_links"], info["n_plaq"], info["n_sites"]
-    masks = [int(m) for m in info["plaq_masks"][:4]] + [lgt.lgt_line_mask(ctx, 0, mu)
-                                                        for mu in range(3)]
-    for _ in range(args.warmup):
-        run_job(lgt, ctx, w, masks, n_sites, n_plaq)
-    lgt.lgt_sync(ctx)
-    lgt.lgt_set_profiling(ctx, max(1, args.event_stride))
-    lgt.lgt_sync(ctx)
-    t0 = time.perf_counter()
-    results = None
-    for _ in range(args.steps):
-        results = run_job(lgt, ctx, w, masks, n_sites, n_plaq)
-    lgt.lgt_sync(ctx)
-    elapsed = time.perf_counter() - t0
-    stats = lgt.lgt_kernel_stats(ctx)
-    lgt.lgt_set_profiling(ctx, False)
-    state_bytes = info["state_bytes"]
-    lgt.lgt_destroy(ctx)
 
-    upd_per_job = len(w.lambdas) * w.n_steps * (1 << n_links) * (n_links + 1)
-    value = args.steps * upd_per_job / elapsed
-    roof = roofline_from_stats(stats, state_bytes, None)
-    if roof:
-        roof["traffic"] = load_traffic(roof["kernel"])
-    trotter_steps = args.steps * len(w.lambdas) * w.n_steps
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    # the headline: the paper's arithmetic (FP64, complex128 amplitudes)
+    head = timed_workload(lgt, w, lgt.LGT_C128, args.steps, args.warmup, args.event_stride)
+    note(f"headline done: {head['value']:.4g} amp-updates/s, {head['us_per_trotter_step']:.1f} us/step")
     line = {
-        "metric": "amp-updates/s", "value": value, "unit": "amp-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "metric": "amp-updates/s", "value": head["value"], "unit": "amp-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["elapsed"] / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": "2x2x2 3+1D Z2 LGT (24 links), symmetric Trotter, 2000 steps, "
-                               "T=100, lambda in {0.2,0.5,1.0,2.0}, complex64 state, FP64 readout",
+                               "T=100, lambda in {0.2,0.5,1.0,2.0}, complex128 state (FP64 "
+                               "arithmetic, as the paper's runs), FP64 readout",
+                   "plan": head["plan"],
                    "trotter_steps_per_bench_step": len(w.lambdas) * w.n_steps,
-                   "us_per_trotter_step": elapsed / trotter_steps * 1e6,
-                   "algorithmic_hbm_frac_per_trotter_step":
-                       (2 * state_bytes / (HBM_PEAK_GBS * 1e9)) / (elapsed / trotter_steps),
-                   "kernel_stats_ms": {k: [int(v[0]), v[1]] for k, v in stats.items()},
+                   "us_per_trotter_step": head["us_per_trotter_step"],
+                   "algorithmic_hbm_frac_per_trotter_step": head["algorithmic_hbm_frac_per_trotter_step"],
+                   "kernel_stats_ms": head["kernel_stats_ms"],
                    "event_stride": max(1, args.event_stride),
-                   "readout": results},
-        "roofline": roof,
+                   "wilson_masks": head["masks"],
+                   "readout": [{k: v for k, v in r.items() if k not in ("plaq", "sigma_x", "stars")}
+                               for r in head["readout"]],
+                   "errors_against_oracle": errors_against_oracle(head["readout"], w)},
+        "roofline": head["roofline"],
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
+        note("cpu baseline done")
     if not args.no_extras:
-        line["lambda_scan"] = lambda_scan(lgt)
-        line["serving"] = serving(lgt, args.serve_requests, args.serve_rate)
-        # offered load below, near and above the mix's service rate (about 20 solves/s)
-        line["serving_load_sweep"] = [serving(lgt, int(4 * r), r) for r in (10.0, 20.0, 40.0)]
-        line["variants"] = variants(lgt)
-        line["bandwidth_sweep"] = bandwidth_sweep(lgt)
-        line["paper_scans"] = paper_scans(lgt)
-        line["phase_estimation"] = phase_estimation(lgt)
-        line["precision"] = precision(lgt)
-        line["precision_long_runs"] = long_run_precision(lgt)
+        steps = [
+            ("complex64", lambda: complex64_line(lgt, w, head["readout"], args.event_stride)),
+            ("roofline_hbm_streaming_32_links", lambda: hbm_rooflines(lgt)),
+            ("config5_4x4", lambda: config5_runs(lgt)),
+            ("lambda_scan", lambda: {"c64": lambda_scan(lgt, lgt.LGT_C64),
+                                     "c128": lambda_scan(lgt, lgt.LGT_C128)}),
+            ("serving", lambda: serving(lgt, args.serve_requests, args.serve_rate)),
+            # offered load below, near and above the mix's service rate (about 25 solves/s)
+            ("serving_load_sweep", lambda: [serving(lgt, int(4 * r), r) for r in (10.0, 20.0, 40.0)]),
+            ("bandwidth_sweep", lambda: {"c64": bandwidth_sweep(lgt, lgt.LGT_C64),
+                                         "c128": bandwidth_sweep(lgt, lgt.LGT_C128)}),
+            ("variants", lambda: variants(lgt)),
+            ("paper_scans", lambda: paper_scans(lgt)),
+            ("phase_estimation", lambda: phase_estimation(lgt)),
+            ("precision_long_runs", lambda: long_run_precision(lgt)),
+        ]
+        for key, fn in steps:
+            t0 = time.perf_counter()
+            line[key] = fn()
+            note(f"{key} done in {time.perf_counter() - t0:.1f} s")
     print(json.dumps(line), flush=True)
 
 

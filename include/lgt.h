@@ -158,6 +158,17 @@ lgt_status lgt_lattice_query(int d, const int *L, int *n_links, int *n_plaq, int
 lgt_status lgt_wilson_mask(const lgt_ctx *ctx, int site, int mu, int nu, int a, int b,
                            uint64_t *mask);
 
+/*
+ * lgt_contour_mask: the Wegner-Wilson contours c1, c2, c3 of Sec. 3.1, whose perimeters are
+ * in the ratios 1 : 1.5 : 2 and enclosed areas 1 : 2 : 3 (perimeter 4, 6, 8 links), as the
+ * boundary of a chain of k = 1, 2, 3 plaquettes starting at site 0.  2D: the plaquette,
+ * the 1 x 2 block along x, the L of three plaquettes.  3D (the paper's figure of the 3D
+ * contours is missing; a planar 1 x 2 block wraps around an extent of 2): the xy plaquette,
+ * plus the xz plaquette sharing its x link, plus the xy plaquette one step up in z.
+ * Host only.  LGT_E_UNSUPPORTED where the chain wraps around the torus (e.g. c2 on 2 x L).
+ */
+lgt_status lgt_contour_mask(const lgt_ctx *ctx, int k, uint64_t *mask);
+
 /* lgt_line_mask: non-contractible loop C_mu through `site` (Sec. 2.1). */
 lgt_status lgt_line_mask(const lgt_ctx *ctx, int site, int mu, uint64_t *mask);
 /*

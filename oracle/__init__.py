@@ -160,6 +160,17 @@ class Lattice:
         """Non-contractible loop C_mu: L_mu links straight along mu (Sec. 2.1)."""
         return self.walk(start_site, [mu + 1] * self.L[mu])
 
+    def contour(self, k: int) -> np.ndarray:
+        """The Wegner-Wilson contours c1, c2, c3 of Sec. 3.1 (perimeters 4 : 6 : 8, areas
+        1 : 2 : 3) as closed walks from site 0.  2D: the unit square, the 1 x 2 rectangle
+        along x, the L of three squares (one on top of the second).  3D (the contour figure
+        is missing; a planar 1 x 2 rectangle would wrap around an extent of 2): the xy
+        square, then bent up the xz face along its x edge, then across the xy face one step
+        up in z."""
+        walks2 = {1: [1, 2, -1, -2], 2: [1, 1, 2, -1, -1, -2], 3: [1, 1, 2, 2, -1, -2, -1, -2]}
+        walks3 = {1: [1, 2, -1, -2], 2: [2, 1, -2, 3, -1, -3], 3: [2, 1, -2, 3, 2, -1, -2, -3]}
+        return self.walk(0, (walks2 if self.d == 2 else walks3)[k])
+
     def thooft(self, mu: int) -> list:
         """Links of the 't Hooft operator V_mu (sigma^x string, Sec. 2.1): the mu-links of
         the sites with coordinate x_mu = 0, which pierce one closed dual surface."""

@@ -633,6 +633,16 @@ lgt_status lgt_line_mask(const lgt_ctx *c, int site, int mu, uint64_t *mask)
     return LGT_OK;
 }
 
+lgt_status lgt_contour_mask(const lgt_ctx *c, int k, uint64_t *mask)
+{
+    if (!c || !mask) return fail(nullptr, LGT_E_INVALID, "null argument");
+    if (k < 1 || k > 3) return fail(const_cast<lgt_ctx *>(c), LGT_E_INVALID, "contour index must be 1, 2 or 3");
+    const uint64_t m = contour_mask(c->lat, k);
+    if (!m) return fail(const_cast<lgt_ctx *>(c), LGT_E_UNSUPPORTED, "the contour wraps around this torus");
+    *mask = m;
+    return LGT_OK;
+}
+
 lgt_status lgt_thooft_mask(const lgt_ctx *c, int mu, uint64_t *mask)
 {
     if (!c || !mask) return fail(nullptr, LGT_E_INVALID, "null argument");

@@ -96,6 +96,31 @@ found:
     return mask;
 }
 
+// The three contours of Sec. 3.1, c1, c2, c3, with perimeters 4 : 6 : 8 and enclosed areas
+// 1 : 2 : 3, each the boundary of a chain of k plaquettes from site 0 (the product of the
+// plaquettes).  2D: one plaquette, two side by side along x, then one more on top of the
+// second (an L).  3D, where a planar 1 x 2 block wraps around an extent of 2: the xy
+// plaquette, the xz plaquette sharing its x link, then the xy plaquette one step up in z
+// (a bent strip).  Returns 0 where the chain's boundary is not a loop of 2k + 2 links (a
+// block that wraps, e.g. c2 on a 2 x L torus).
+uint64_t contour_mask(const Lattice &lat, int k)
+{
+    const int d = lat.d, planes = d * (d - 1) / 2;
+    auto plaq = [&](int s, int plane) { return lat.plaq_mask[(size_t)s * planes + plane]; };
+    uint64_t m = 0;
+    if (d == 2) {
+        const int s1 = lat.fwd[0 * d + 0], s2 = lat.fwd[s1 * d + 1];
+        const int chain[3] = {0, s1, s2};
+        for (int i = 0; i < k; ++i) m ^= plaq(chain[i], 0);
+    } else {
+        // planes of a 3D site: 0 = (x, y), 1 = (x, z), 2 = (y, z)
+        const int up = lat.fwd[0 * d + 2];
+        const int site[3] = {0, 0, up}, plane[3] = {0, 1, 0};
+        for (int i = 0; i < k; ++i) m ^= plaq(site[i], plane[i]);
+    }
+    return __builtin_popcountll(m) == 2 * k + 2 ? m : 0;
+}
+
 uint64_t line_mask(const Lattice &lat, int site, int mu)
 {
     uint64_t m = 0;

@@ -33,6 +33,7 @@ struct Lattice {
 std::string build_lattice(int d, const int *L, Lattice &out);
 uint64_t region_mask(const Lattice &lat, int site, int mu, int nu, int a, int b);
 uint64_t line_mask(const Lattice &lat, int site, int mu);
+uint64_t contour_mask(const Lattice &lat, int k);   // c1..c3 of Sec. 3.1, 0 if degenerate
 uint64_t thooft_mask(const Lattice &lat, int mu);
 
 // Plaquette syndrome tables: P(b) = XOR_k tab[k][(b >> 8k) & 255], bit p of P(b)

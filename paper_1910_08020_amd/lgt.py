@@ -98,6 +98,7 @@ _SIGNATURES = [
     ("lgt_plan_describe", ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_size_t]),
     ("lgt_set_plan", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lgt_thooft_mask", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
+    ("lgt_contour_mask", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
     ("lgt_apply_pauli", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_uint64]),
     ("lgt_apply_gate", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]),
     ("lgt_set_graphs", ctypes.c_int, [_VP, ctypes.c_int]),
@@ -344,6 +345,12 @@ def lgt_scan(ctx, sched: lgt_schedule, order, first_step, substeps, n_points, ma
 def lgt_thooft_mask(ctx, mu) -> int:
     m = ctypes.c_uint64()
     _check(lib().lgt_thooft_mask(ctx, mu, ctypes.byref(m)), ctx)
+    return m.value
+
+
+def lgt_contour_mask(ctx, k) -> int:
+    m = ctypes.c_uint64()
+    _check(lib().lgt_contour_mask(ctx, k, ctypes.byref(m)), ctx)
     return m.value
 
 

@@ -14,7 +14,11 @@ imports nothing from the GPU library.  The workloads are the seeded inputs of ``
 H(s) = -lambda sum sigma^x - s sum U_p with s = j/n at the right end of step j (Sec. 2.2),
 start |+>^N, expectations divided by the norm (Sec. 2.4).
 
+* ``config5_dual.json``: the 4x4 torus (32 links), 1000 symmetric steps, T = 50, lambda in
+  {0.5, 1.0, 1.5}: every <U_p> and <sigma^x_l> from the exact Wegner-dual image.
+
 Usage: python tests/golden/make_golden.py config2
+       python tests/golden/make_golden.py config5
        python tests/golden/make_golden.py config3 [lambda ...]
 """
 from __future__ import annotations
@@ -90,12 +94,40 @@ def config3(lams):
         print(f"config3 lambda={lam} done in {time.time() - t0:.1f} s", flush=True)
 
 
+def config5():
+    """4x4 torus (32 links), 1000 symmetric steps, T = 50, lambda in {0.5, 1.0, 1.5}: every
+    <U_p> and <sigma^x_l> from the exact Wegner-dual image (2^16 amplitudes, oracle/dual.py),
+    the full state being too large for the host."""
+    from oracle.dual import DualIsing
+    w = workloads.CONFIG5
+    lat = oracle.Lattice(w.d, w.L)
+    D = DualIsing(lat.plaq, lat.N)
+    out = {"_about": "4x4 torus, 1000 symmetric Trotter steps, T = 50, start |+>^32, "
+                     "H(s) = -lambda sum sigma^x - s sum U_p, s = j/n (Sec. 2.2, eq. (s)); "
+                     "<U_p> and <sigma^x_l> of the exact Wegner-dual transverse-field Ising "
+                     "image (oracle/dual.py); written by tests/golden/make_golden.py from the "
+                     "oracle only", "workload": w.name, "results": {}}
+    for lam in w.lambdas:
+        t0 = time.time()
+        dt, cx, cz = oracle.schedule_plaquette_ramp(w.T, w.n_steps, lam, 1.0)
+        phi = D.evolve(D.ghz(), dt, cx, cz, w.order)
+        plaq = [D.expect_tx(phi, [p]) for p in range(lat.n_plaq)]
+        sx = [D.expect_bond(phi, q) for q in range(lat.N)]
+        out["results"][repr(lam)] = {"lambda": lam, "plaq": plaq, "sigma_x": sx,
+                                     "energy": float(-cx[-1] * np.sum(sx) - cz[-1] * np.sum(plaq))}
+        print(f"config5 lambda={lam} done in {time.time() - t0:.1f} s", flush=True)
+    with open(os.path.join(HERE, "config5_dual.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "config2"
     if what == "config2":
         config2()
+    elif what == "config5":
+        config5()
     elif what == "config3":
         lams = [float(x) for x in sys.argv[2:]] or list(workloads.CONFIG3.lambdas)
         config3(lams)
     else:
-        raise SystemExit("usage: make_golden.py config2 | config3 [lambda ...]")
+        raise SystemExit("usage: make_golden.py config2 | config5 | config3 [lambda ...]")

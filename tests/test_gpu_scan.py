@@ -113,3 +113,50 @@ def test_paper_scan_2x2x2_symmetric():
     for gq in (0.5, 0.6, 0.7, 0.8, 0.9):
         i, j = int(round(gq * 1000)) - 1, int(round(1000 / gq)) - 1
         assert abs(z[i] - x[j]) < 0.02, gq
+
+
+@pytest.mark.parametrize("d,L", [(2, (3, 3)), (2, (4, 4)), (3, (2, 2, 2))], ids=["3x3", "4x4", "2x2x2"])
+def test_contour_masks_match_oracle(d, L):
+    """The Wegner-Wilson contours c1, c2, c3 of Sec. 3.1 (perimeters 4, 6, 8)."""
+    lat = oracle.Lattice(d, L)
+    with gpu_ctx(d, L, C64) as ctx:
+        for k in (1, 2, 3):
+            assert lgt.lgt_contour_mask(ctx, k) == _mask(lat.contour(k))
+        with pytest.raises(lgt.LgtError) as ex:
+            lgt.lgt_contour_mask(ctx, 4)
+        assert ex.value.status == lgt.LGT_E_INVALID
+    with gpu_ctx(2, (2, 2), C64) as ctx:       # a 1 x 2 block wraps around an extent of 2
+        with pytest.raises(lgt.LgtError) as ex:
+            lgt.lgt_contour_mask(ctx, 2)
+        assert ex.value.status == lgt.LGT_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("d,L,n_pts,sub", [(2, (3, 3), 8, 5), (3, (2, 2, 2), 2, 2)],
+                         ids=["3x3", "2x2x2"])
+def test_contour_scan_matches_oracle(d, L, n_pts, sub):
+    lat = oracle.Lattice(d, L)
+    loops = [lat.contour(k) for k in (1, 2, 3)]
+    got = _gpu_scan(d, L, C128, 2.0, n_pts, sub, 0.3, SYM, [_mask(x) for x in loops])
+    want = oracle.adiabatic_scan(lat, oracle.zground_state(lat), 2.0, n_pts, sub, 0.3, SYM,
+                                 loops=loops)
+    assert np.max(np.abs(got - want)) < 1e-10
+
+
+def test_wilson_loop_laws_3x3():
+    """Sec. 3.1: on the adiabatic state, log<W_c2>/log<W_c1> and log<W_c3>/log<W_c1> start at
+    the perimeter ratios 1.5 and 2 (the second-order perturbative result for small g) and
+    move towards the area ratios 2 and 3 deep in the confined phase (exact ground state of
+    the dual Ising model at g = 2: 1.93 and 2.84).  The paper's 3x3 first-order schedule,
+    n = 500, t_s = 0.02, complex64."""
+    lat = oracle.Lattice(2, (3, 3))
+    with gpu_ctx(2, (3, 3), C64) as ctx:
+        masks = [lgt.lgt_contour_mask(ctx, k) for k in (1, 2, 3)]
+        lgt.lgt_reset(ctx, lgt.LGT_INIT_ZGROUND, 0)
+        s = lgt.make_schedule(0.02 * 2000, 500 * 2000, ramp=lgt.LGT_RAMP_COUPLING, g0=0.0, g1=2.0)
+        rows = lgt.lgt_scan(ctx, s, TROT, 0, 500, 2000, masks)
+    g, w = rows[:, 0], rows[:, 5:8]
+    r2, r3 = np.log(w[:, 1]) / np.log(w[:, 0]), np.log(w[:, 2]) / np.log(w[:, 0])
+    small = (g > 0.049) & (g < 0.101)
+    assert np.all(np.abs(r2[small] - 1.5) < 0.05) and np.all(np.abs(r3[small] - 2.0) < 0.08)
+    assert r2[-1] > 1.8 and r3[-1] > 2.6
+    assert lat.n_plaq == 9

@@ -186,3 +186,37 @@ def test_walk_loops():
     # non-contractible line has L links all of one direction
     line = lat.line(0, 1)
     assert len(line) == 3
+
+
+@pytest.mark.parametrize("d,L", [(2, (3, 3)), (2, (4, 4)), (3, (2, 2, 2))], ids=["3x3", "4x4", "2x2x2"])
+def test_wilson_contours(d, L):
+    """Sec. 3.1: c1, c2, c3 have perimeters in the ratios 1 : 1.5 : 2 and enclose 1 : 2 : 3
+    plaquettes.  Each walk is a closed contractible loop (even overlap with every 't Hooft
+    surface), its length is the perimeter, and its links are exactly the boundary (the
+    symmetric difference) of a chain of 1, 2, 3 plaquettes of the lattice's plaquette list."""
+    lat = Lattice(d, L)
+    plaq_sets = [set(int(q) for q in p) for p in lat.plaq]
+    for k, per in ((1, 4), (2, 6), (3, 8)):
+        c = set(int(q) for q in lat.contour(k))
+        assert len(c) == per
+        for mu in range(d):
+            assert len(c & set(lat.thooft(mu))) % 2 == 0
+        # some chain of k distinct plaquettes has c as its boundary (brute force)
+        found = False
+        for combo in itertools.combinations(range(lat.n_plaq), k):
+            b = set()
+            for p in combo:
+                b ^= plaq_sets[p]
+            if b == c:
+                found = True
+                break
+        assert found, k
+    # the area ratios distinguish the laws: no chain of fewer plaquettes bounds c2 or c3
+    for k in (2, 3):
+        c = set(int(q) for q in lat.contour(k))
+        for j in range(1, k):
+            for combo in itertools.combinations(range(lat.n_plaq), j):
+                b = set()
+                for p in combo:
+                    b ^= plaq_sets[p]
+                assert b != c
