@@ -441,7 +441,18 @@ __global__ __launch_bounds__(64 << W) void k_tile(const DevInst *__restrict__ in
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t n_tiles = 1ull << (n - TB);
     const int lowb = LOW ? 0 : hb - CB;
-    auto tile_base = [&](uint64_t tile) -> uint64_t {
+    // Rows shorter than a 128-byte cache line (complex128 rows of 4 amplitudes) leave the
+    // other half of each line to the tile next to it (tile index ^ 1).  Workgroups go to the
+    // eight XCDs in turn, each with its own L2, so tiles t and t ^ 1 are placed on one XCD:
+    // tile bit 0 comes from bit 3 of the walk index and bits 1..3 from bits 0..2, which makes
+    // walk indices p and p ^ 8 (same XCD, same round) the two halves of every line.
+    constexpr bool HALF_LINE_ROWS = !LOW && (sizeof(C) << CB) < 128;
+    auto tile_of = [&](uint64_t p) -> uint64_t {
+        if constexpr (HALF_LINE_ROWS) return (p & ~15ull) | ((p & 7) << 1) | ((p >> 3) & 1);
+        else return p;
+    };
+    auto tile_base = [&](uint64_t walk) -> uint64_t {
+        const uint64_t tile = tile_of(walk);
         if constexpr (LOW) return tile << TB;
         else return ((tile & ((1ull << lowb) - 1)) << CB) | ((tile >> lowb) << (hb + TB - CB));
     };
@@ -1273,6 +1284,8 @@ bool pass_offsets_fit(int dtype, int n, int low, int hb, int h, int cb)
     if (w < 0) return false;
     if (low) return n >= 10 + w;
     const int eb = dtype == LGT_C64 ? 3 : 4;
+    // half-line rows pair tiles in blocks of 16 (k_tile's tile_of): at least 16 tiles
+    if (dtype != LGT_C64 && cb == 2 && n - (10 + w) < 4) return false;
     return hb >= cb && hb + h <= n && hb + (6 + w - cb) + eb <= 32;
 }
 
