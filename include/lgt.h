@@ -349,6 +349,18 @@ lgt_status lgt_crossing(const double *g, const double *a, const double *b, int n
  */
 lgt_status lgt_sample(lgt_ctx *ctx, uint64_t n_shots, uint64_t seed, uint64_t *out);
 
+/*
+ * lgt_sample_noalloc: lgt_sample for callers that cannot allocate device memory (code
+ * between graph captures, serving loops and harnesses that forbid hipMalloc): the same
+ * shots, bit for bit, with no hipMalloc, hipFree or other allocation.  The block sums and
+ * the shots live in a fixed array of 16 MiB per GPU, kept until the process ends: at most
+ * 2^20 shots and states of at most 30 qubits, else LGT_E_INVALID.  Every call on one GPU
+ * uses that GPU's array, so calls on one GPU that overlap in time (two threads, or two
+ * streams) race and must be serialised by the caller.  The call returns when the shots are
+ * in out[0..n_shots-1] (host memory).
+ */
+lgt_status lgt_sample_noalloc(lgt_ctx *ctx, uint64_t n_shots, uint64_t seed, uint64_t *out);
+
 /* State transfer: host buffer of exactly info.state_bytes in the context's dtype. */
 lgt_status lgt_get_state(lgt_ctx *ctx, void *host, size_t bytes);
 lgt_status lgt_set_state(lgt_ctx *ctx, const void *host, size_t bytes);

@@ -1351,6 +1351,26 @@ lgt_status lgt_sample(lgt_ctx *c, uint64_t n_shots, uint64_t seed, uint64_t *out
     return LGT_OK;
 }
 
+lgt_status lgt_sample_noalloc(lgt_ctx *c, uint64_t n_shots, uint64_t seed, uint64_t *out)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (!out) return fail(c, LGT_E_INVALID, "null output");
+    if (n_shots < 1 || n_shots > (uint64_t)kScratchShots)
+        return fail(c, LGT_E_INVALID, "n_shots must be in [1, 2^20] for the allocation-free sampler");
+    const int n = nq(c);
+    if (((uint64_t)1 << (n - sample_block_bits(n))) > (uint64_t)kScratchSums)
+        return fail(c, LGT_E_INVALID, "the allocation-free sampler takes states of at most 30 qubits");
+    void *scr = nullptr;
+    HIPCHK(c, scratch_address(c->device, &scr));
+    // launched untimed: the profiling events come from a pool the library may need to grow
+    HIPCHK(c, launch_sample_scratch(c->dtype, c->state, n, n_shots, seed, scr, c->stream));
+    HIPCHK(c, hipMemcpyAsync(out, (uint64_t *)scr + kScratchSums, n_shots * sizeof(uint64_t),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LGT_OK;
+}
+
 lgt_status lgt_get_state(lgt_ctx *c, void *host, size_t bytes)
 {
     lgt_status s = check_ctx(c);

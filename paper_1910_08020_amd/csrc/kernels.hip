@@ -16,7 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 #include <algorithm>
-
+#include <mutex>
 #include <type_traits>
 
 #include "lgt_internal.hpp"
@@ -1140,6 +1140,48 @@ __global__ __launch_bounds__(256) void k_sample(const cplx_t<T> *__restrict__ ps
     out[i] = found ? pick : last_nz;
 }
 
+// inclusive prefix of the block sums in place, ascending, by one thread: the same additions
+// in the same order as the host prefix of launch_sample, so both give the same bits
+__global__ void k_prefix_seq(double *sums, int nb)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double acc = 0;
+    for (int i = 0; i < nb; ++i) {
+        acc += sums[i];
+        sums[i] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free sampling entry point: block sums (kScratchSums doubles)
+// then shots (kScratchShots words).  One copy per device, held until the process ends.
+// Host code never uses the array's name as an address: scratch_address() looks up the
+// device address once per device with hipGetSymbolAddress.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint64_t scratch[kScratchSums + kScratchShots];
+
+hipError_t scratch_address(int device, void **out)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -1584,6 +1626,34 @@ hipError_t launch_sum_cols(const double *partials, int rows, int width, int ncol
 }
 
 int sample_block_bits(int n) { return n < kSampleBlockBits ? n : kSampleBlockBits; }
+
+hipError_t launch_sample_scratch(int dtype, const void *psi, int n, uint64_t n_shots,
+                                 uint64_t seed, void *scratch_dev, hipStream_t st)
+{
+    const uint64_t nb = 1ull << (n - sample_block_bits(n));
+    if (nb > (uint64_t)kScratchSums || n_shots < 1 || n_shots > (uint64_t)kScratchShots)
+        return hipErrorInvalidValue;
+    double *sums = (double *)scratch_dev;
+    uint64_t *shots = (uint64_t *)scratch_dev + kScratchSums;
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_block_sums<float>, dim3((unsigned)nb), dim3(256), 0, st,
+                           (const float2 *)psi, n, sums);
+    else
+        hipLaunchKernelGGL(k_block_sums<double>, dim3((unsigned)nb), dim3(256), 0, st,
+                           (const double2 *)psi, n, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prefix_seq, dim3(1), dim3(64), 0, st, sums, (int)nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const unsigned g = (unsigned)((n_shots + 255) / 256);
+    if (dtype == LGT_C64)
+        hipLaunchKernelGGL(k_sample<float>, dim3(g), dim3(256), 0, st, (const float2 *)psi, n,
+                           sums, (int)nb, n_shots, seed, shots);
+    else
+        hipLaunchKernelGGL(k_sample<double>, dim3(g), dim3(256), 0, st, (const double2 *)psi, n,
+                           sums, (int)nb, n_shots, seed, shots);
+    return hipGetLastError();
+}
 
 hipError_t launch_sample(int dtype, const void *psi, int n, uint64_t n_shots, uint64_t seed,
                          double *block_sums, double *block_prefix, uint64_t *out_dev,

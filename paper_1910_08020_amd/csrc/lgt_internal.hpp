@@ -224,6 +224,18 @@ hipError_t launch_reduce_dos(int dtype, const void *psi, int n, const uint32_t *
                              int n_plaq, double *partials, hipStream_t st);
 // sampling: block sums -> prefix -> inverse CDF
 int sample_block_bits(int n);
+// Allocation-free sampling: a static device array per GPU holds the block sums
+// (kScratchSums doubles: states of up to 30 qubits at 2^10 amplitudes per block) and the
+// shots (kScratchShots words).  scratch_address gives its device address on `device`,
+// taken once per device with hipGetSymbolAddress.  launch_sample_scratch runs the same
+// kernels as launch_sample with the prefix on the device (same additions, same order) and
+// leaves the shots at word kScratchSums of the array.
+constexpr int kScratchSums = 1 << 20;
+constexpr int kScratchShots = 1 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_address(int device, void **out);
+hipError_t launch_sample_scratch(int dtype, const void *psi, int n, uint64_t n_shots,
+                                 uint64_t seed, void *scratch_dev, hipStream_t st);
 hipError_t launch_sample(int dtype, const void *psi, int n, uint64_t n_shots, uint64_t seed,
                          double *block_sums, double *block_prefix, uint64_t *out_dev,
                          hipStream_t st);

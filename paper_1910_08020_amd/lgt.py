@@ -88,6 +88,7 @@ _SIGNATURES = [
     ("lgt_evolve", ctypes.c_int, [_VP, ctypes.POINTER(lgt_schedule), ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64]),
     ("lgt_measure", ctypes.c_int, [_VP, ctypes.POINTER(lgt_observable), _dp, ctypes.c_size_t]),
     ("lgt_sample", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
+    ("lgt_sample_noalloc", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
     ("lgt_get_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
     ("lgt_set_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
     ("lgt_copy_state", ctypes.c_int, [_VP, _VP]),
@@ -260,6 +261,13 @@ def lgt_measure(ctx, kind, masks=None, cx=0.0, cz=0.0, out_len=None) -> np.ndarr
 def lgt_sample(ctx, n_shots, seed) -> np.ndarray:
     out = np.zeros(n_shots, dtype=np.uint64)
     _check(lib().lgt_sample(ctx, n_shots, seed, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), ctx)
+    return out
+
+
+def lgt_sample_noalloc(ctx, n_shots, seed) -> np.ndarray:
+    out = np.zeros(n_shots, dtype=np.uint64)
+    _check(lib().lgt_sample_noalloc(ctx, n_shots, seed,
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), ctx)
     return out
 
 
