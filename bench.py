@@ -44,15 +44,21 @@ def _lgt():
 
 
 def kernel_source_hash() -> str:
-    """Hash of the kernel sources (kernels.hip and the tile layouts) with comments and blank
-    space removed: counter readings stay valid across edits of comments and of the host
-    sources."""
-    src = ""
-    for name in ("kernels.hip", "tile_layout.hpp"):
-        with open(os.path.join(ROOT, "paper_1910_08020_amd", "csrc", name)) as fh:
-            src += fh.read()
+    """Hash of the tile-pass sources: the device code of kernels.hip up to the register
+    passes (helpers, k_low, k_tile), its launchers (launch_pass_nt, launch_pass_t) and the tile
+    layouts, with comments, includes and blank space removed.  Counter readings of the tile passes stay
+    valid across edits of other kernels, of comments and of the host sources."""
+    with open(os.path.join(ROOT, "paper_1910_08020_amd", "csrc", "kernels.hip")) as fh:
+        k = fh.read()
+    src = k[:k.index("// high pass: link qubits")]
+    for fn in ("launch_pass_nt", "launch_pass_t"):
+        m = re.search(r"static hipError_t " + fn + r"\(.*?\n}\n", k, flags=re.S)
+        src += m.group(0) if m else ""
+    with open(os.path.join(ROOT, "paper_1910_08020_amd", "csrc", "tile_layout.hpp")) as fh:
+        src += fh.read()
     src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
     src = re.sub(r"//[^\n]*", " ", src)
+    src = re.sub(r"#include[^\n]*", " ", src)
     src = " ".join(src.split())
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
@@ -690,7 +696,7 @@ def main():
                          "of known size for counter calibration); prints no benchmark line")
     ap.add_argument("--profile-lattice", default="2x2x2",
                     help="profiling runs only: the torus, e.g. 2x7 or 4x4")
-    ap.add_argument("--profile-dtype", default="c128", choices=("c64", "c128"),
+    ap.add_argument("--profile-dtype", default="c64", choices=("c64", "c128"),
                     help="profiling runs only: the amplitude type")
     args = ap.parse_args()
     if args.gpus != 1:
