@@ -313,6 +313,7 @@ def lambda_scan(lgt, dtype, steps=None):
         orders = [w.order] * len(ctxs)
         for c in ctxs:
             lgt.lgt_reset(c, lgt.LGT_INIT_PLUS, 0)
+        group = lgt.lgt_batch_tune(ctxs, 32)                      # instances per launch
         lgt.lgt_batch_evolve(ctxs, scheds, orders, 0, n)          # warm-up
         lgt.lgt_sync(ctxs[0])
         for c in ctxs:
@@ -337,6 +338,7 @@ def lambda_scan(lgt, dtype, steps=None):
     k = len(w.lambdas)
     name = "complex64" if dtype == lgt.LGT_C64 else "complex128"
     return {"workload": f"3x3 (18 links), {k} lambdas, {n} symmetric steps, {name}",
+            "tuned_instances_per_launch": group,
             "batched_solves_per_s": k / t_batch, "per_instance_solves_per_s": k / t_single,
             "speedup": t_single / t_batch, "batched_s": t_batch, "per_instance_s": t_single}
 

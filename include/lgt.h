@@ -433,11 +433,28 @@ const char *lgt_last_error(const lgt_ctx *ctx);
  * synchronised first.  States that each fit in 160 MiB but together do not (e.g.
  * 24-link complex64 states, 128 MiB each) run in groups of at most 160 MiB, one group
  * after the other on its first context's stream, the call waiting for each group, so
- * that a group's state stays in the 256 MB Infinity Cache between passes.  Errors as
- * lgt_evolve; LGT_E_INVALID if the contexts do not share lattice and dtype.
+ * that a group's state stays in the 256 MB Infinity Cache between passes; a group size
+ * chosen by lgt_batch_tune (or lgt_batch_set_group) on ctxs[0] replaces that rule.  Errors
+ * as lgt_evolve; LGT_E_INVALID if the contexts do not share lattice and dtype.
  */
 lgt_status lgt_batch_evolve(int n, lgt_ctx *const *ctxs, const lgt_schedule *scheds,
                             const lgt_order *orders, int64_t first_step, int64_t count);
+
+/*
+ * lgt_batch_tune: autotuner for the number of instances per launch of lgt_batch_evolve over
+ * these n contexts (same lattice and dtype).  Times `steps` identity steps (u = 1, v = 0 and
+ * unit phases, which leave every state bit for bit unchanged) with the instances in launch
+ * groups of each candidate size (all n in one launch, the Infinity-Cache-sized group, n/2,
+ * n/4, ..., 1), the groups one after the other on ctxs[0]'s stream, and keeps the fastest
+ * size in ctxs[0]; later lgt_batch_evolve calls whose first context is ctxs[0] run their
+ * instances in groups of that size.  *group receives the choice.  Every grouping gives the
+ * same results bit for bit.  States of <= 12 links run every instance in one on-chip
+ * launch and keep one group.  1 <= steps <= 1024.
+ * lgt_batch_set_group: set that size directly (0 = the built-in rule: groups whose states
+ * fit the Infinity Cache together, else one group), e.g. to reuse a tuned size.
+ */
+lgt_status lgt_batch_tune(int n, lgt_ctx *const *ctxs, int steps, int *group);
+lgt_status lgt_batch_set_group(lgt_ctx *ctx, int group);
 
 /*
  * lgt_set_graphs: on != 0 makes lgt_batch_evolve calls whose first context is ctx capture

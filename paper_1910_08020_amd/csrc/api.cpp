@@ -62,6 +62,7 @@ struct lgt_ctx {
     int64_t prof_launches[KF_COUNT] = {0};
     double prof_ms[KF_COUNT] = {0};
     int plan = 0;   // pass plan code (plan_passes), 0 = built-in rule
+    int batch_group = 0;   // instances per launch group of batches led by this context, 0 = rule
     int n_anc = 0;  // 1: one ancilla qubit on bit N_l above the links
     // captured launch sequences of batched evolutions, by structure (lgt_set_graphs)
     bool use_graphs = false;
@@ -1563,6 +1564,9 @@ lgt_status lgt_tune(lgt_ctx *c, int steps)
     return LGT_OK;
 }
 
+static lgt_status batch_group_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule *scheds,
+                                     const lgt_order *orders, int64_t first_step, int64_t count);
+
 lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule *scheds,
                             const lgt_order *orders, int64_t first_step, int64_t count)
 {
@@ -1584,15 +1588,17 @@ lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule
     lgt_status s = check_ctx(c0);
     if (s) return fail(nullptr, s, c0->err);
     if (count == 0) return LGT_OK;
-    // States that each fit the 256 MB Infinity Cache but together do not run in groups
-    // that do, one group after the other: four 24-link complex64 states (128 MiB each) in
-    // one launch took 61 us per instance-step, one at a time 57 us.  Each instance's
-    // arithmetic is the same either way.
-    const size_t per_group = kCacheStateBytes / c0->state_bytes;
+    // Instances per launch: the tuned group size of the first context (lgt_batch_tune), else
+    // states that each fit the 256 MB Infinity Cache but together do not run in groups that
+    // do, one group after the other (four 24-link complex64 states, 128 MiB each, in one
+    // launch took 61 us per instance-step, one at a time 57 us).  Each instance's arithmetic
+    // is the same either way.
+    const size_t per_group = c0->batch_group > 0 ? (size_t)c0->batch_group
+                                                 : kCacheStateBytes / c0->state_bytes;
     if (per_group >= 1 && (size_t)n_inst > per_group) {
         for (int i0 = 0; i0 < n_inst; i0 += (int)per_group) {
             const int m = (int)std::min<size_t>(per_group, (size_t)(n_inst - i0));
-            if ((s = lgt_batch_evolve(m, ctxs + i0, scheds + i0, orders + i0, first_step, count)))
+            if ((s = batch_group_evolve(m, ctxs + i0, scheds + i0, orders + i0, first_step, count)))
                 return s;
             // the next group starts once this one has left the cache
             if (hipStreamSynchronize(ctxs[i0]->stream) != hipSuccess)
@@ -1600,6 +1606,17 @@ lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule
         }
         return LGT_OK;
     }
+    return batch_group_evolve(n_inst, ctxs, scheds, orders, first_step, count);
+}
+
+}  // extern "C"
+
+// one launch group of a batch: every pass one launch over the n_inst instances
+static lgt_status batch_group_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule *scheds,
+                                     const lgt_order *orders, int64_t first_step, int64_t count)
+{
+    lgt_ctx *c0 = ctxs[0];
+    lgt_status s = LGT_OK;
     // every instance's tables in one staging block, built on several host threads (the
     // FP32 rounding of a 2000-step table takes milliseconds per instance).  Complex64 runs of
     // tile passes round and upload their phase rows in chunks of 32, 64, 128, ... steps,
@@ -1737,6 +1754,123 @@ lgt_status lgt_batch_evolve(int n_inst, lgt_ctx *const *ctxs, const lgt_schedule
     for (int i = 1; i < n_inst; ++i)
         if (ctxs[i]->stream != c0->stream && hipStreamSynchronize(c0->stream) != hipSuccess)
             return fail(nullptr, LGT_E_DEVICE, "batch sync");
+    return LGT_OK;
+}
+
+extern "C" {
+
+lgt_status lgt_batch_set_group(lgt_ctx *c, int group)
+{
+    lgt_status s = check_ctx(c);
+    if (s) return s;
+    if (group < 0 || group > 65535) return fail(c, LGT_E_INVALID, "group size must be in [0, 65535]");
+    c->batch_group = group;
+    return LGT_OK;
+}
+
+lgt_status lgt_batch_tune(int n, lgt_ctx *const *ctxs, int steps, int *group_out)
+{
+    if (n < 1 || n > 65535 || !ctxs || !ctxs[0] || !group_out)
+        return fail(nullptr, LGT_E_INVALID, "bad batch tune arguments");
+    if (steps < 1 || steps > 1024) return fail(nullptr, LGT_E_INVALID, "steps must be in [1, 1024]");
+    lgt_ctx *c0 = ctxs[0];
+    for (int i = 0; i < n; ++i) {
+        lgt_ctx *c = ctxs[i];
+        if (!c || c->dtype != c0->dtype || c->lat.d != c0->lat.d ||
+            std::memcmp(c->lat.L, c0->lat.L, sizeof c->lat.L) != 0 || c->device != c0->device)
+            return fail(nullptr, LGT_E_INVALID, "batch contexts must share lattice, dtype and device");
+        if (c->n_anc) return fail(nullptr, LGT_E_UNSUPPORTED, "batches run the fused form: no ancilla contexts");
+    }
+    lgt_status s = check_ctx(c0);
+    if (s) return fail(nullptr, s, c0->err);
+    const Lattice &lat = c0->lat;
+    const int N = lat.n_links;
+    if (small_supported(c0->dtype, N)) {
+        // one on-chip kernel runs every instance and step of a batch: one launch group
+        c0->batch_group = n;
+        *group_out = n;
+        return LGT_OK;
+    }
+    for (int i = 0; i < n; ++i)
+        if (hipStreamSynchronize(ctxs[i]->stream) != hipSuccess)
+            return fail(nullptr, LGT_E_DEVICE, "sync of a batch member failed");
+    // identity tables, as in lgt_tune: u = 1, v = 0 and unit phases leave every state bit for
+    // bit unchanged
+    const int np1 = lat.n_plaq + 1, total = steps + 2;
+    const size_t eb = elem_bytes(c0->dtype);
+    std::vector<char> rot((size_t)total * eb, 0), ph((size_t)total * np1 * eb, 0);
+    for (int j = 0; j < total; ++j) {
+        if (c0->dtype == LGT_C64) ((float *)rot.data())[2 * j] = 1.0f;
+        else ((double *)rot.data())[2 * j] = 1.0;
+    }
+    for (int k = 0; k < total * np1; ++k) {
+        if (c0->dtype == LGT_C64) ((float *)ph.data())[2 * k] = 1.0f;
+        else ((double *)ph.data())[2 * k] = 1.0;
+    }
+    void *drot = nullptr, *dph = nullptr;
+    DevInst *dinst = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&] {
+        (void)hipStreamSynchronize(c0->stream);
+        if (drot) (void)hipFree(drot);
+        if (dph) (void)hipFree(dph);
+        if (dinst) (void)hipFree(dinst);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    std::vector<DevInst> di(n);
+    hipError_t e = hipMalloc(&drot, rot.size());
+    if (e == hipSuccess) e = hipMalloc(&dph, ph.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&dinst, sizeof(DevInst) * n);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (int i = 0; i < n; ++i) {
+        di[i] = DevInst{};
+        di[i].psi = ctxs[i]->state;
+        di[i].rot = drot;
+        di[i].phase = dph;
+        di[i].ptab = c0->ptab_dev;
+        di[i].n_total = total;
+    }
+    if (e == hipSuccess) e = hipMemcpy(drot, rot.data(), rot.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dph, ph.data(), ph.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dinst, di.data(), sizeof(DevInst) * n, hipMemcpyHostToDevice);
+    // candidates: every instance in one launch, the Infinity-Cache-sized group, halves, ..., one
+    std::vector<int> cands{n};
+    const size_t cache_group = kCacheStateBytes / c0->state_bytes;
+    if (cache_group >= 1 && cache_group < (size_t)n) cands.push_back((int)cache_group);
+    for (int g = (n + 1) / 2; g >= 1; g = (g == 1) ? 0 : (g + 1) / 2)
+        if (std::find(cands.begin(), cands.end(), g) == cands.end()) cands.push_back(g);
+    std::vector<uint8_t> forms(total, kFormTan);
+    int best = n;
+    float best_ms = 1e30f;
+    for (int g : cands) {
+        if (e != hipSuccess) break;
+        auto run = [&](int count) -> hipError_t {
+            for (int i0 = 0; i0 < n; i0 += g) {
+                const int m = std::min(g, n - i0);
+                hipError_t r = enqueue_fused_steps(c0->dtype, N, lat.n_plaq, dinst + i0, m, count, -1,
+                                                   0, forms.data(), c0->plan, c0->stream, nullptr);
+                if (r != hipSuccess) return r;
+            }
+            return hipSuccess;
+        };
+        e = run(2);
+        if (e == hipSuccess) e = hipEventRecord(e0, c0->stream);
+        if (e == hipSuccess) e = run(steps);
+        if (e == hipSuccess) e = hipEventRecord(e1, c0->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = g;
+        }
+    }
+    cleanup();
+    if (e != hipSuccess) return fail(nullptr, LGT_E_DEVICE, std::string("batch tune: ") + hipGetErrorString(e));
+    c0->batch_group = best;
+    *group_out = best;
     return LGT_OK;
 }
 

@@ -111,6 +111,8 @@ _SIGNATURES = [
     ("lgt_get_plan", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int)]),
     ("lgt_last_error", ctypes.c_char_p, [_VP]),
     ("lgt_batch_evolve", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_VP), ctypes.POINTER(lgt_schedule), ctypes.POINTER(ctypes.c_int), ctypes.c_int64, ctypes.c_int64]),
+    ("lgt_batch_tune", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    ("lgt_batch_set_group", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lgt_server_create", ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)]),
     ("lgt_server_submit", ctypes.c_int, [_VP, ctypes.POINTER(lgt_request), ctypes.POINTER(ctypes.c_uint64)]),
     ("lgt_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(lgt_result)]),
@@ -397,6 +399,18 @@ def lgt_batch_evolve(ctxs, scheds, orders, first_step=0, count=None):
     if count is None:
         count = scheds[0].n_steps - first_step
     _check(lib().lgt_batch_evolve(n, arr_c, arr_s, arr_o, first_step, count))
+
+
+def lgt_batch_tune(ctxs, steps=8) -> int:
+    n = len(ctxs)
+    arr_c = (_VP * n)(*[c.value if isinstance(c, _VP) else c for c in ctxs])
+    g = ctypes.c_int()
+    _check(lib().lgt_batch_tune(n, arr_c, steps, ctypes.byref(g)))
+    return g.value
+
+
+def lgt_batch_set_group(ctx, group):
+    _check(lib().lgt_batch_set_group(ctx, group), ctx)
 
 
 def lgt_server_create(hbm_budget, max_slots, chunk_steps):

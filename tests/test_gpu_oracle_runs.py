@@ -444,3 +444,46 @@ def test_config5_full_run_matches_dual_oracle(dtype, dual_4x4):
     assert np.max(np.abs(sx - want_sx)) < tol
     assert np.max(np.abs(st - 1)) < tol
     assert abs(nrm - 1) < (1e-10 if dtype == C128 else 1e-4)
+
+
+def test_batch_tuner_groups_match_single_runs_and_oracle():
+    """The instances-per-launch tuner leaves every state as it was, and batches run in the
+    tuned group size, or any size set by hand, equal single runs bit for bit and the oracle."""
+    lat = oracle.Lattice(2, (3, 3))
+    lams = LAMS[:12]
+    n = 40
+    ctxs = [lgt.lgt_create(2, [3, 3], 1, C128) for _ in lams]
+    try:
+        states = [workloads.random_state(lat.N, stream=80 + i) for i in range(len(lams))]
+        for c, psi in zip(ctxs, states):
+            lgt.lgt_set_state(c, psi)
+        g = lgt.lgt_batch_tune(ctxs, 16)
+        assert 1 <= g <= len(lams)
+        for c, psi in zip(ctxs, states):
+            assert np.array_equal(get_state(c), psi)
+        scheds = [lgt.make_schedule(0.05 * n, n, lam, 1.0) for lam in lams]
+        results = {}
+        for group in (g, 5, 0):
+            lgt.lgt_batch_set_group(ctxs[0], group)
+            for c, psi in zip(ctxs, states):
+                lgt.lgt_set_state(c, psi)
+            lgt.lgt_batch_evolve(ctxs, scheds, [SYM] * len(lams), 0, n)
+            results[group] = [get_state(c) for c in ctxs]
+        with pytest.raises(lgt.LgtError) as e:
+            lgt.lgt_batch_set_group(ctxs[0], -1)
+        assert e.value.status == lgt.LGT_E_INVALID
+    finally:
+        for c in ctxs:
+            lgt.lgt_destroy(c)
+    for i, (lam, psi) in enumerate(zip(lams, states)):
+        dt, cx, cz = oracle.schedule_plaquette_ramp(0.05 * n, n, lam, 1.0)
+        want = oracle.evolve(np.array(psi), lat, dt, cx, cz, SYM)
+        assert np.array_equal(results[g][i], results[5][i]) and np.array_equal(results[g][i], results[0][i])
+        assert np.max(np.abs(results[g][i] - want)) < 1e-10
+    # states held on chip: one launch runs every instance
+    small = [lgt.lgt_create(2, [2, 2], 1, C64) for _ in range(6)]
+    try:
+        assert lgt.lgt_batch_tune(small, 4) == 6
+    finally:
+        for c in small:
+            lgt.lgt_destroy(c)
