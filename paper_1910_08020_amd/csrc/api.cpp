@@ -303,7 +303,9 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
     // persistent tile passes: one low tile (12 bits for plan 1, the largest otherwise), then
     // as few high tiles as possible with the longest (plans 1, 2) or shortest (3) rows;
     // chunks no tile pass takes go to register passes
-    const int low = (plan == 1 || n_links < big) ? 12 : big;
+    // plan 5: complex128 low tiles of 14 bits (one bit in registers)
+    int low = (plan == 1 || n_links < big) ? 12 : big;
+    if (plan == 5 && dtype != LGT_C64 && n_links >= 15) low = 14;
     p.pass[p.n_passes++] = Pass{PASS_TILE_LOW, 0, low, 0};
     const bool long_rows = plan != 3;
     const int rest = n_links - low, reg_max = dtype == LGT_C64 ? 6 : 5;
@@ -313,7 +315,7 @@ PassPlan plan_passes(int n_links, int dtype, int plan, int n_inst)
     // passes stream HBM (one of the 28-link high passes runs 7-13% faster with them)
     const int cb_hi = dtype == LGT_C64 ? (n_links >= 26 ? 6 : 5) : 4;
     // most bits one high tile rotates: 10 (complex64, 128-byte rows, 16 waves), 11
-    // (complex128, 64-byte rows, 8 waves)
+    // (complex128: 128-byte rows with one bit in registers, or 64-byte rows; 8 waves)
     const int hmax = dtype == LGT_C64 ? 10 : 11;
     const int nh = (rest + hmax - 1) / hmax;
     int q = low;
@@ -1478,7 +1480,7 @@ lgt_status lgt_set_plan(lgt_ctx *c, int plan)
 {
     lgt_status s = check_ctx(c);
     if (s) return s;
-    if (plan < 0 || (plan & ~kPlanNoMerge) > 4) return fail(c, LGT_E_INVALID, "unknown plan code");
+    if (plan < 0 || (plan & ~kPlanNoMerge) > 5) return fail(c, LGT_E_INVALID, "unknown plan code");
     c->plan = plan;
     return LGT_OK;
 }
@@ -1540,7 +1542,7 @@ lgt_status lgt_tune(lgt_ctx *c, int steps)
     int best = c->plan;
     float best_ms = 1e30f;
     std::vector<std::string> seen;
-    for (int cand : {1, 2, 3, 4}) {
+    for (int cand : {1, 2, 3, 4, 5}) {
         if (e != hipSuccess) break;
         const std::string d = describe_plan(plan_passes(n, c->dtype, cand, 1), n);
         if (std::find(seen.begin(), seen.end(), d) != seen.end()) continue;

@@ -555,6 +555,153 @@ __global__ __launch_bounds__(64 << W) void k_tile(const DevInst *__restrict__ in
 }
 
 // ---------------------------------------------------------------------------
+// Tile with one more rotated bit kept in registers.  The tile is that of k_tile's
+// geometry <T, W, ROWB> taken twice: once with index bit R clear and once with it set,
+// R the bit above the tile's rotated bits (TB for a low tile, hb+TB-CB for a high tile).
+// A thread holds both halves in 32 registers and rotates bit R between them; the other
+// bits are rotated as in k_tile, one half at a time through LDS.  With complex128 this
+// gives a high tile of 11 bits over full 128-byte rows (k_tile needs 64-byte rows for 11
+// bits) or a low tile of 14 bits, so a 24-link step is two passes either way.  The 32
+// registers leave no room for a prefetch buffer: the next tile is loaded once the
+// current one is stored.
+// ---------------------------------------------------------------------------
+constexpr int kRbStaggerSleeps = 40;   // s_sleep 8 (512 clocks) each
+
+template <typename T, int W, int ROWB, bool TAN, bool TN, bool MERGE>
+__global__ __launch_bounds__(64 << W) void k_tile_rb(const DevInst *__restrict__ insts, int n,
+                                                     int hb, int step, int pre, int post,
+                                                     int n_plaq)
+{
+    using C = cplx_t<T>;
+    using G = PassGeom<T, W, ROWB>;
+    using MG = MergeGeom<T, W, ROWB>;
+    constexpr bool LOW = G::LOW;
+    constexpr int TB = G::TB, CB = G::CB;
+    constexpr MergeLayout M = MG::M;
+    __shared__ C buf[1 << TB];
+    __shared__ uint32_t ptab[kPtabWords];
+    __shared__ C ph_pre[MERGE ? 1 : kMaxPlaq + 1], ph_post[kMaxPlaq + 1];
+    static_assert(MERGE || TN == TAN, "single-step passes have one form");
+
+    const DevInst in = insts[blockIdx.y];
+    if (in.step0 + step >= in.n_total) return;
+    const gp<const RotParam<T>> rot = (gp<const RotParam<T>>)in.rot;
+    const RotParam<T> rp = ldg(rot + (in.step0 + step));
+    if ((rp.u == T(1)) != TAN) return;
+    const T tt = TAN ? rp.v : rp.u;
+    T tn = tt;
+    const bool more = MERGE && in.step0 + step + 1 < in.n_total;
+    if (more) {
+        const RotParam<T> rq = ldg(rot + (in.step0 + step + 1));
+        if ((rq.u == T(1)) != TN) return;
+        tn = TN ? rq.v : rq.u;
+    } else if (TN != TAN) {
+        return;
+    }
+    const gp<C> psi = (gp<C>)in.psi;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rbit = LOW ? TB : hb + TB - CB;             // the register bit R
+    const uint64_t n_tiles = 1ull << (n - TB - 1);
+    const int lowb = LOW ? 0 : hb - CB;
+    auto tile_base = [&](uint64_t tile) -> uint64_t {
+        if constexpr (LOW) return tile << (TB + 1);
+        else return ((tile & ((1ull << lowb) - 1)) << CB) | ((tile >> lowb) << (rbit + 1));
+    };
+    auto spread = [&](int o) -> uint64_t {
+        if constexpr (LOW) return (uint64_t)o;
+        else return (uint64_t)(o & ((1 << CB) - 1)) | ((uint64_t)(o >> CB) << hb);
+    };
+    auto gbit = [&](int i) -> int { return (LOW || i < CB) ? i : hb + (i - CB); };
+    const int oA = l | (w << 6), oB = MG::thrB(l, w);
+    const int sA = MG::swz(oA), sB = MG::swz(oB);
+    const uint32_t thrA = (uint32_t)spread(oA), thrBg = (uint32_t)spread(oB);
+    const uint64_t rofs = 1ull << rbit;
+    const bool phased = MERGE || pre >= 0 || post >= 0;
+    uint32_t pra[16], prb[16], qR = 0;
+    if (phased) {
+        load_tables<T>(in, n_plaq, MERGE ? -1 : pre, post, ptab, ph_pre, ph_post);
+        __syncthreads();
+        uint32_t qa[4], qb[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            qa[k] = link_set(gbit(6 + W + k), ptab);
+            qb[k] = link_set(gbit(M.reg[k]), ptab);
+        }
+        reg_sets(qa, pra);
+        reg_sets(qb, prb);
+        qR = link_set(rbit, ptab);
+    }
+    C x[32];
+    // Every workgroup loads, computes and stores its tiles in turn, and all of them start
+    // together, so the chip would alternate between all loading and all computing.  Half
+    // of the workgroups of each XCD (walk bit 3) start about 20000 clocks later (a third
+    // of a tile period), which keeps loads of one half under the arithmetic of the other:
+    // 24-link complex128 high pass 112 -> 100 us.
+    if (n_tiles > gridDim.x && ((blockIdx.x >> 3) & 1))
+        for (int i = 0; i < kRbStaggerSleeps; ++i) __builtin_amdgcn_s_sleep(8);
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint64_t base = tile_base(tile);
+        const gp<C> tp = psi + base;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            x[r] = ldg((gp<const C>)tp + spread(r << (6 + W)) + thrA);
+            x[16 + r] = ldg((gp<const C>)tp + rofs + spread(r << (6 + W)) + thrA);
+        }
+        if (!MERGE && pre >= 0) {
+            const uint32_t P0 = syndrome(base + thrA, ptab);
+            apply_phase_pr<C>(x, P0, pra, ph_pre);
+            apply_phase_pr<C>(x + 16, P0 ^ qR, pra, ph_pre);
+        }
+        // bit R of this step, then every tile bit, one half at a time
+#pragma unroll
+        for (int r = 0; r < 16; ++r) rot_pair_s<TAN, T, C>(x[r], x[16 + r], tt);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            C *y = x + 16 * h;
+            rot_lanes<TAN, M.al, T, C>(y, tt);
+            rot_regs_s<TAN, 15, T, C>(y, tt);
+            // a thread writes exactly the slots it read last: no barrier before the write
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[sA + (r << (6 + W))] = y[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 16; ++r) y[r] = buf[sB + MG::regB(r)];
+            rot_regs_s<TAN, M.br1, T, C>(y, tt);
+            rot_lanes<TAN, M.bl, T, C>(y, tt);
+            if (MERGE || post >= 0)
+                apply_phase_pr<C>(y, syndrome(base + thrBg, ptab) ^ (h ? qR : 0u), prb, ph_post);
+            if (more) {
+                rot_regs_s<TN, 15, T, C>(y, tn);
+                rot_lanes<TN, M.bl, T, C>(y, tn);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[sB + MG::regB(r)] = y[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 16; ++r) y[r] = buf[sA + (r << (6 + W))];
+            if (more) {
+                rot_regs_s<TN, M.ar2, T, C>(y, tn);
+                rot_lanes<TN, M.al, T, C>(y, tn);
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) rot_pair_s<TN, T, C>(x[r], x[16 + r], tn);
+        }
+        // the store addresses are formed again here: kept from the loads they would hold
+        // 64 more registers through the tile
+        uint64_t sbase = base;
+        asm volatile("" : "+s"(sbase));
+        const gp<C> sp = psi + sbase;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            stg(sp + spread(r << (6 + W)) + thrA, x[r]);
+            stg(sp + rofs + spread(r << (6 + W)) + thrA, x[16 + r]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // high pass: link qubits [q0, q0+H) from registers, lanes on consecutive amplitudes
 // ---------------------------------------------------------------------------
 constexpr int kHighThreads = 256;
@@ -1302,17 +1449,57 @@ static hipError_t launch_pass_t(const DevInst *dev_inst, int n_inst, int n, int 
     return launch_pass_nt<T, W, ROWB, false>(dev_inst, n, hb, step, pre, post, n_plaq, forms, merge, g, b, st);
 }
 
+// the register-bit tiles (k_tile_rb): one resident workgroup per CU, tiles of 2^(TB+1)
+template <typename T, int W, int ROWB>
+static hipError_t launch_pass_rb(const DevInst *dev_inst, int n_inst, int n, int hb, int step,
+                                 int pre, int post, int n_plaq, int forms, int merge,
+                                 hipStream_t st)
+{
+    constexpr int TB = 10 + W;
+    const uint64_t n_tiles = 1ull << (n - TB - 1);
+    uint64_t slots = 256 / (uint64_t)n_inst;
+    if (slots < 1) slots = 1;
+    const uint64_t rounds = (n_tiles + slots - 1) / slots;
+    const uint64_t grid = (n_tiles + rounds - 1) / rounds;
+    const dim3 g((unsigned)grid, (unsigned)n_inst), b(64 << W);
+    if (merge) {
+        if (pre >= 0 || post < 0) return hipErrorInvalidValue;
+        const int fa = forms & 3, fb = (forms >> 2) & 3;
+        if (fa & 1) {
+            launch_timed(k_tile_rb<T, W, ROWB, true, true, true>, g, b, st, dev_inst, n, hb, step, -1, post, n_plaq);
+            if (fb & 2)
+                launch_timed(k_tile_rb<T, W, ROWB, true, false, true>, g, b, st, dev_inst, n, hb, step, -1, post, n_plaq);
+        }
+        if (fa & 2) {
+            launch_timed(k_tile_rb<T, W, ROWB, false, false, true>, g, b, st, dev_inst, n, hb, step, -1, post, n_plaq);
+            if (fb & 1)
+                launch_timed(k_tile_rb<T, W, ROWB, false, true, true>, g, b, st, dev_inst, n, hb, step, -1, post, n_plaq);
+        }
+        return hipGetLastError();
+    }
+    if (forms & 1)
+        launch_timed(k_tile_rb<T, W, ROWB, true, true, false>, g, b, st, dev_inst, n, hb, step, pre, post, n_plaq);
+    if (forms & 2)
+        launch_timed(k_tile_rb<T, W, ROWB, false, false, false>, g, b, st, dev_inst, n, hb, step, pre, post, n_plaq);
+    return hipGetLastError();
+}
+
 int pass_wave_bits(int dtype, int low, int h, int cb)
 {
     // low tile of h = 10+W bits, 2 <= W <= 4 (complex64) / 3 (complex128).  High tile with
     // rows of 2^cb amplitudes rotates (6-cb) lane bits + 4 register bits + W wave bits;
     // rows of 128, 256 or 512 bytes (complex64), 128 or 256 bytes (complex128), and for
-    // complex128 also 64-byte rows with eight waves: 11 rotated bits in 128 KiB of LDS, so
-    // that a 24-link complex128 step takes two tile passes (13 + 11 bits) instead of three
+    // complex128 also 64-byte rows with eight waves: 11 rotated bits in 128 KiB of LDS.
+    // Complex128 with 128-byte rows and h = 11 is the register-bit tile (k_tile_rb, eight
+    // waves, one more rotated bit in registers).  Either gives a 24-link complex128 step
+    // two tile passes (13 + 11 bits) instead of three.
+    // Complex128 low tiles of 14 bits are register-bit tiles too (eight waves).
     const int wmax = dtype == LGT_C64 ? 4 : 3;
+    if (low && dtype != LGT_C64 && h == 14) return 3;
     if (low) return (h - 10 >= 2 && h - 10 <= wmax) ? h - 10 : -1;
     const int cb_lo = dtype == LGT_C64 ? 4 : 2, cb_hi = dtype == LGT_C64 ? 6 : 4;
     if (cb < cb_lo || cb > cb_hi) return -1;
+    if (dtype != LGT_C64 && cb == 3 && h == 11) return 3;
     const int w = h - (10 - cb);
     if (w < 0 || w > wmax) return -1;
     if (dtype != LGT_C64 && cb == 2 && w != 3) return -1;
@@ -1324,10 +1511,12 @@ bool pass_offsets_fit(int dtype, int n, int low, int hb, int h, int cb)
     // per-thread element offsets of a high tile must stay below 2^32 bytes
     const int w = pass_wave_bits(dtype, low, h, cb);
     if (w < 0) return false;
-    if (low) return n >= 10 + w;
+    if (low) return n >= h;
     const int eb = dtype == LGT_C64 ? 3 : 4;
     // half-line rows pair tiles in blocks of 16 (k_tile's tile_of): at least 16 tiles
     if (dtype != LGT_C64 && cb == 2 && n - (10 + w) < 4) return false;
+    // the register-bit tile spans 2^(11+w) amplitudes: at least one tile
+    if (dtype != LGT_C64 && cb == 3 && h == 11 && n < 11 + w) return false;
     return hb >= cb && hb + h <= n && hb + (6 + w - cb) + eb <= 32;
 }
 
@@ -1364,12 +1553,14 @@ hipError_t launch_tile(int dtype, const DevInst *dev_inst, int n_inst, int n, in
         return launch_pass_t<float, 4, 5>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st);
     }
     if (low) {
+        if (h == 14) return launch_pass_rb<double, 3, 13>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, merge, st);
         if (w == 2) return launch_pass_t<double, 2, 12>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, merge, st);
         return launch_pass_t<double, 3, 13>(dev_inst, n_inst, n, 0, step, pre, post, n_plaq, forms, merge, st);
     }
     if (cb == 2) {
         if (w == 3) return launch_pass_t<double, 3, 2>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st);
     } else if (cb == 3) {
+        if (h == 11) return launch_pass_rb<double, 3, 3>(dev_inst, n_inst, n, hb, step, pre, post, n_plaq, forms, merge, st);
         LGT_PASS_CASES(double, 3)
     } else {
         LGT_PASS_CASES(double, 4)

@@ -395,7 +395,7 @@ def test_plan_description_small_state():
         lgt.lgt_tune(ctx, 2)
 
 
-PLANS = [0, 1, 2, 3, 4, lgt.LGT_PLAN_NO_MERGE, 2 | lgt.LGT_PLAN_NO_MERGE]
+PLANS = [0, 1, 2, 3, 4, 5, lgt.LGT_PLAN_NO_MERGE, 2 | lgt.LGT_PLAN_NO_MERGE, 5 | lgt.LGT_PLAN_NO_MERGE]
 
 
 @pytest.mark.parametrize("order", [TROT, SYM], ids=["trotter", "symmetric"])
@@ -424,7 +424,7 @@ def test_every_plan_matches_oracle(d, L, order):
 
 def test_set_plan_rejects_unknown_codes():
     with gpu_ctx(2, (2, 4), C64) as ctx:
-        for bad in (-1, 5, 7, 13, 16):
+        for bad in (-1, 6, 7, 14, 16):
             with pytest.raises(lgt.LgtError) as ex:
                 lgt.lgt_set_plan(ctx, bad)
             assert ex.value.status == lgt.LGT_E_INVALID
