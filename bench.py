@@ -45,13 +45,13 @@ def _lgt():
 
 def kernel_source_hash() -> str:
     """Hash of the tile-pass sources: the device code of kernels.hip up to the register
-    passes (helpers, k_low, k_tile), its launchers (launch_pass_nt, launch_pass_t) and the tile
-    layouts, with comments, includes and blank space removed.  Counter readings of the tile passes stay
+    passes (helpers, k_low, k_tile, k_tile_rb), their launchers (launch_pass_nt, launch_pass_t,
+    launch_pass_rb) and the tile layouts, with comments, includes and blank space removed.  Counter readings of the tile passes stay
     valid across edits of other kernels, of comments and of the host sources."""
     with open(os.path.join(ROOT, "paper_1910_08020_amd", "csrc", "kernels.hip")) as fh:
         k = fh.read()
     src = k[:k.index("// high pass: link qubits")]
-    for fn in ("launch_pass_nt", "launch_pass_t"):
+    for fn in ("launch_pass_nt", "launch_pass_t", "launch_pass_rb"):
         m = re.search(r"static hipError_t " + fn + r"\(.*?\n}\n", k, flags=re.S)
         src += m.group(0) if m else ""
     with open(os.path.join(ROOT, "paper_1910_08020_amd", "csrc", "tile_layout.hpp")) as fh:
