@@ -401,7 +401,11 @@ lgt_status lgt_kernel_stats(lgt_ctx *ctx, const char **names, int64_t *launches,
  * lgt_set_plan: pick the plan by code, e.g. to reuse what lgt_tune chose in another process
  * (lgt_get_plan reads it back).  0 = built-in rule; 1 = 12-bit low tile, then high tiles
  * with the longest rows; 2 = the largest low tile (14 bits complex64, 13 complex128), then
- * as 1; 3 = as 2 with the shortest rows; 4 = 12-bit LDS tile and register passes only.
+ * as 1; 3 = as 2 with the shortest rows; 4 = 12-bit LDS tile and register passes only;
+ * 5 = complex128 only: a 14-bit low tile that keeps one link in registers, then as 1
+ * (complex64: as 2).  With complex128 the longest-row high tile of 11 links (plans 1, 2 at
+ * 24 links) also keeps one link in registers, over rows of 8 amplitudes; plan 3 takes rows
+ * of 4 amplitudes there instead.
  * Adding LGT_PLAN_NO_MERGE keeps one launch per pass and step.  Without it, tile plans
  * walk their passes forwards and backwards on alternate steps, so that the pass ending one
  * step also starts the next and applies both rotations around the phase in one launch
@@ -413,6 +417,12 @@ lgt_status lgt_kernel_stats(lgt_ctx *ctx, const char **names, int64_t *launches,
 #define LGT_PLAN_NO_MERGE 8
 lgt_status lgt_tune(lgt_ctx *ctx, int steps);
 lgt_status lgt_plan_describe(const lgt_ctx *ctx, char *out, size_t len);
+/* lgt_plan_query: the plan lgt_plan_describe would show for a context of n_links links
+ * (1..34), dtype LGT_C64 / LGT_C128 and plan code `plan` (as lgt_set_plan), computed on the
+ * host without a context or a GPU: "tile_low<h>" covers links 0..h-1, "tile_high(q<q>,h<h>,
+ * rows<r>)" and "reg_high(q<q>,h<h>)" links q..q+h-1, every link exactly once per step.
+ * E_INVALID for arguments out of range or a buffer shorter than the text. */
+lgt_status lgt_plan_query(int n_links, lgt_dtype dtype, int plan, char *out, size_t len);
 lgt_status lgt_set_plan(lgt_ctx *ctx, int plan);
 lgt_status lgt_get_plan(const lgt_ctx *ctx, int *plan);
 

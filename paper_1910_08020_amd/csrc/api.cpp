@@ -1476,6 +1476,17 @@ lgt_status lgt_plan_describe(const lgt_ctx *c, char *out, size_t len)
     return d.size() < len ? LGT_OK : fail(const_cast<lgt_ctx *>(c), LGT_E_INVALID, "buffer too short");
 }
 
+lgt_status lgt_plan_query(int n_links, lgt_dtype dtype, int plan, char *out, size_t len)
+{
+    if (!out || len == 0) return fail(nullptr, LGT_E_INVALID, "null argument");
+    if (n_links < 1 || n_links > kMaxLinks) return fail(nullptr, LGT_E_INVALID, "n_links out of range");
+    if (dtype != LGT_C64 && dtype != LGT_C128) return fail(nullptr, LGT_E_INVALID, "unknown dtype");
+    if (plan < 0 || (plan & ~kPlanNoMerge) > 5) return fail(nullptr, LGT_E_INVALID, "unknown plan code");
+    const std::string d = describe_plan(plan_passes(n_links, dtype, plan, 1), n_links);
+    std::snprintf(out, len, "%s", d.c_str());
+    return d.size() < len ? LGT_OK : fail(nullptr, LGT_E_INVALID, "buffer too short");
+}
+
 lgt_status lgt_set_plan(lgt_ctx *c, int plan)
 {
     lgt_status s = check_ctx(c);

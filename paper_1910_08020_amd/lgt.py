@@ -97,6 +97,7 @@ _SIGNATURES = [
     ("lgt_kernel_stats", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64), _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     ("lgt_tune", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lgt_plan_describe", ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_size_t]),
+    ("lgt_plan_query", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]),
     ("lgt_set_plan", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lgt_thooft_mask", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
     ("lgt_contour_mask", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
@@ -314,6 +315,12 @@ def lgt_tune(ctx, steps=8):
 def lgt_plan_describe(ctx) -> str:
     buf = ctypes.create_string_buffer(512)
     _check(lib().lgt_plan_describe(ctx, buf, 512), ctx)
+    return buf.value.decode()
+
+
+def lgt_plan_query(n_links, dtype, plan=0) -> str:
+    buf = ctypes.create_string_buffer(512)
+    _check(lib().lgt_plan_query(n_links, dtype, plan, buf, 512), None)
     return buf.value.decode()
 
 

@@ -1,0 +1,86 @@
+"""Pass plans on the host (lgt_plan_query, no GPU): for every lattice size and plan code the
+passes of one Trotter step rotate every link exactly once (the link layer of Sec. 2.2 is a
+product of commuting single-link rotations, so any partition of the links into passes
+applies it), rows stay below the rotated bits, and merging happens only between tile passes."""
+import re
+
+import pytest
+
+from paper_1910_08020_amd import lgt
+
+PLAN_CODES = [0, 1, 2, 3, 4, 5, lgt.LGT_PLAN_NO_MERGE, 2 | lgt.LGT_PLAN_NO_MERGE,
+              5 | lgt.LGT_PLAN_NO_MERGE]
+
+
+def parse(desc):
+    """[(kind, first link, count, row amplitudes)], merged flag"""
+    merged = desc.endswith(" ; steps merged")
+    body = desc[: -len(" ; steps merged")] if merged else desc
+    passes = []
+    for part in body.split(" | "):
+        if m := re.fullmatch(r"tile_low(\d+)", part):
+            passes.append(("low", 0, int(m.group(1)), 0))
+        elif part == "low12":
+            passes.append(("low", 0, 12, 0))
+        elif m := re.fullmatch(r"tile_high\(q(\d+),h(\d+),rows(\d+)\)", part):
+            passes.append(("high", int(m.group(1)), int(m.group(2)), int(m.group(3))))
+        elif m := re.fullmatch(r"reg_high\(q(\d+),h(\d+)\)", part):
+            passes.append(("reg", int(m.group(1)), int(m.group(2)), 0))
+        else:
+            raise AssertionError(f"unparsed pass {part!r} in {desc!r}")
+    return passes, merged
+
+
+@pytest.mark.parametrize("dtype", [lgt.LGT_C64, lgt.LGT_C128], ids=["c64", "c128"])
+def test_every_plan_rotates_every_link_once(dtype):
+    amp = 8 if dtype == lgt.LGT_C64 else 16
+    for n in range(13, 35):
+        for plan in PLAN_CODES:
+            desc = lgt.lgt_plan_query(n, dtype, plan)
+            passes, merged = parse(desc)
+            seen = []
+            for kind, q, h, rows in passes:
+                seen += range(q, q + h)
+                if kind == "high":
+                    assert rows & (rows - 1) == 0 and rows <= (1 << q), desc
+                    assert rows * amp >= 64, desc          # at least half a 128-byte line
+                    # at most 2^14 amplitudes a tile (complex128 holds 2^13 in LDS and,
+                    # for 11 links over 8-amplitude rows, one more link in registers)
+                    tile_bits = h + rows.bit_length() - 1
+                    assert tile_bits <= 14, desc
+                    if dtype == lgt.LGT_C128 and tile_bits == 14:
+                        assert (h, rows) == (11, 8), desc
+            assert sorted(seen) == list(range(n)), (n, plan, desc)
+            if merged:
+                assert not plan & lgt.LGT_PLAN_NO_MERGE and len(passes) >= 2, desc
+                assert passes[0][0] != "reg" and passes[-1][0] != "reg", desc
+            elif not plan & lgt.LGT_PLAN_NO_MERGE and plan != 4 and len(passes) >= 2:
+                assert "reg" in (passes[0][0], passes[-1][0]), desc
+
+
+def test_small_states_run_on_chip():
+    for n in range(1, 13):
+        for dtype in (lgt.LGT_C64, lgt.LGT_C128):
+            assert lgt.lgt_plan_query(n, dtype, 0) == f"small({n} links on chip)"
+
+
+def test_plans_of_the_benchmark_lattices():
+    q = lgt.lgt_plan_query
+    # 24 links: two tile passes, one merged launch per step
+    assert q(24, lgt.LGT_C64) == "tile_low14 | tile_high(q14,h10,rows16) ; steps merged"
+    assert q(24, lgt.LGT_C128) == "tile_low13 | tile_high(q13,h11,rows8) ; steps merged"
+    assert q(24, lgt.LGT_C128, 3) == "tile_low13 | tile_high(q13,h11,rows4) ; steps merged"
+    assert q(24, lgt.LGT_C128, 5) == "tile_low14 | tile_high(q14,h10,rows8) ; steps merged"
+    assert q(24, lgt.LGT_C64, 5) == q(24, lgt.LGT_C64, 2)
+    # 32 links: three passes
+    assert q(32, lgt.LGT_C64) == ("tile_low14 | tile_high(q14,h9,rows32) | "
+                                  "tile_high(q23,h9,rows32) ; steps merged")
+    assert q(24, lgt.LGT_C128, 2 | lgt.LGT_PLAN_NO_MERGE).count("|") == 1
+
+
+def test_plan_query_rejects_bad_arguments():
+    for args in ((0, lgt.LGT_C64, 0), (35, lgt.LGT_C64, 0), (24, 2, 0), (24, lgt.LGT_C64, 6),
+                 (24, lgt.LGT_C64, -1), (24, lgt.LGT_C64, 14)):
+        with pytest.raises(lgt.LgtError) as ex:
+            lgt.lgt_plan_query(*args)
+        assert ex.value.status == lgt.LGT_E_INVALID
