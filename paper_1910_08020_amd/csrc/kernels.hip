@@ -565,7 +565,7 @@ __global__ __launch_bounds__(64 << W) void k_tile(const DevInst *__restrict__ in
 // registers leave no room for a prefetch buffer: the next tile is loaded once the
 // current one is stored.
 // ---------------------------------------------------------------------------
-constexpr int kRbStaggerSleeps = 40;   // s_sleep 8 (512 clocks) each
+constexpr int kRbStaggerSleeps = 20;   // s_sleep 8 (512 clocks) each
 
 template <typename T, int W, int ROWB, bool TAN, bool TN, bool MERGE>
 __global__ __launch_bounds__(64 << W) void k_tile_rb(const DevInst *__restrict__ insts, int n,
@@ -632,35 +632,37 @@ __global__ __launch_bounds__(64 << W) void k_tile_rb(const DevInst *__restrict__
         qR = link_set(rbit, ptab);
     }
     C x[32];
-    // Every workgroup loads, computes and stores its tiles in turn, and all of them start
-    // together, so the chip would alternate between all loading and all computing.  Half
-    // of the workgroups of each XCD (walk bit 3) start about 20000 clocks later (a third
-    // of a tile period), which keeps loads of one half under the arithmetic of the other:
-    // 24-link complex128 high pass 112 -> 100 us.
+    // A tile's halves go through LDS one after the other: both to layout B (the rotations of
+    // `step` before the exchange and after it), then bit R and the phase on both halves
+    // in registers, then each half back to layout A and out.  A half's registers take the
+    // next tile's loads as soon as that half is stored, so its loads run under the other
+    // half's arithmetic and under the first half of the next tile.
+    // All workgroups start together and would keep loading at the same time and computing
+    // at the same time; half of the workgroups of each XCD (walk bit 3) start about
+    // kRbStaggerSleeps x 512 clocks later, so that one half loads while the other computes.
     if (n_tiles > gridDim.x && ((blockIdx.x >> 3) & 1))
         for (int i = 0; i < kRbStaggerSleeps; ++i) __builtin_amdgcn_s_sleep(8);
-    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const uint64_t base = tile_base(tile);
-        const gp<C> tp = psi + base;
+    uint64_t tile = blockIdx.x;
+    if (tile >= n_tiles) return;
+    auto load_half = [&](uint64_t t_id, int h) __attribute__((always_inline)) {
+        const gp<const C> tq = (gp<const C>)psi + tile_base(t_id) + (h ? rofs : 0);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            x[r] = ldg((gp<const C>)tp + spread(r << (6 + W)) + thrA);
-            x[16 + r] = ldg((gp<const C>)tp + rofs + spread(r << (6 + W)) + thrA);
-        }
-        if (!MERGE && pre >= 0) {
-            const uint32_t P0 = syndrome(base + thrA, ptab);
-            apply_phase_pr<C>(x, P0, pra, ph_pre);
-            apply_phase_pr<C>(x + 16, P0 ^ qR, pra, ph_pre);
-        }
-        // bit R of this step, then every tile bit, one half at a time
-#pragma unroll
-        for (int r = 0; r < 16; ++r) rot_pair_s<TAN, T, C>(x[r], x[16 + r], tt);
+        for (int r = 0; r < 16; ++r) x[16 * h + r] = ldg(tq + spread(r << (6 + W)) + thrA);
+    };
+    load_half(tile, 0);
+    load_half(tile, 1);
+    for (;;) {
+        const uint64_t base = tile_base(tile), next = tile + gridDim.x;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             C *y = x + 16 * h;
+            if (!MERGE && pre >= 0)
+                apply_phase_pr<C>(y, syndrome(base + thrA, ptab) ^ (h ? qR : 0u), pra, ph_pre);
             rot_lanes<TAN, M.al, T, C>(y, tt);
             rot_regs_s<TAN, 15, T, C>(y, tt);
-            // a thread writes exactly the slots it read last: no barrier before the write
+            // the first half writes exactly the slots this thread read last; the second
+            // half's slots may still be read by other threads as their B slots
+            if (h) __syncthreads();
 #pragma unroll
             for (int r = 0; r < 16; ++r) buf[sA + (r << (6 + W))] = y[r];
             __syncthreads();
@@ -668,21 +670,14 @@ __global__ __launch_bounds__(64 << W) void k_tile_rb(const DevInst *__restrict__
             for (int r = 0; r < 16; ++r) y[r] = buf[sB + MG::regB(r)];
             rot_regs_s<TAN, M.br1, T, C>(y, tt);
             rot_lanes<TAN, M.bl, T, C>(y, tt);
-            if (MERGE || post >= 0)
-                apply_phase_pr<C>(y, syndrome(base + thrBg, ptab) ^ (h ? qR : 0u), prb, ph_post);
-            if (more) {
-                rot_regs_s<TN, 15, T, C>(y, tn);
-                rot_lanes<TN, M.bl, T, C>(y, tn);
-            }
+        }
+        // bit R, the phase, and bit R of step + 1: both halves in layout B
 #pragma unroll
-            for (int r = 0; r < 16; ++r) buf[sB + MG::regB(r)] = y[r];
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < 16; ++r) y[r] = buf[sA + (r << (6 + W))];
-            if (more) {
-                rot_regs_s<TN, M.ar2, T, C>(y, tn);
-                rot_lanes<TN, M.al, T, C>(y, tn);
-            }
+        for (int r = 0; r < 16; ++r) rot_pair_s<TAN, T, C>(x[r], x[16 + r], tt);
+        if (MERGE || post >= 0) {
+            const uint32_t P0 = syndrome(base + thrBg, ptab);
+            apply_phase_pr<C>(x, P0, prb, ph_post);
+            apply_phase_pr<C>(x + 16, P0 ^ qR, prb, ph_post);
         }
         if (more) {
 #pragma unroll
@@ -694,10 +689,31 @@ __global__ __launch_bounds__(64 << W) void k_tile_rb(const DevInst *__restrict__
         asm volatile("" : "+s"(sbase));
         const gp<C> sp = psi + sbase;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            stg(sp + spread(r << (6 + W)) + thrA, x[r]);
-            stg(sp + rofs + spread(r << (6 + W)) + thrA, x[16 + r]);
+        for (int h = 0; h < 2; ++h) {
+            C *y = x + 16 * h;
+            if (more) {
+                rot_regs_s<TN, 15, T, C>(y, tn);
+                rot_lanes<TN, M.bl, T, C>(y, tn);
+            }
+            // the first half writes the B slots this thread read last; the second half's
+            // may still be read by other threads as their A slots
+            if (h) __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[sB + MG::regB(r)] = y[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 16; ++r) y[r] = buf[sA + (r << (6 + W))];
+            if (more) {
+                rot_regs_s<TN, M.ar2, T, C>(y, tn);
+                rot_lanes<TN, M.al, T, C>(y, tn);
+            }
+            const gp<C> hp = sp + (h ? rofs : 0);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) stg(hp + spread(r << (6 + W)) + thrA, y[r]);
+            if (next < n_tiles) load_half(next, h);
         }
+        if (next >= n_tiles) break;
+        tile = next;
     }
 }
 
