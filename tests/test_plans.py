@@ -76,6 +76,12 @@ def test_plans_of_the_benchmark_lattices():
     assert q(32, lgt.LGT_C64) == ("tile_low14 | tile_high(q14,h9,rows32) | "
                                   "tile_high(q23,h9,rows32) ; steps merged")
     assert q(24, lgt.LGT_C128, 2 | lgt.LGT_PLAN_NO_MERGE).count("|") == 1
+    # 32 links complex128: the register-bit low tile keeps both high passes on 256-byte rows
+    assert q(32, lgt.LGT_C128) == ("tile_low14 | tile_high(q14,h9,rows16) | "
+                                   "tile_high(q23,h9,rows16) ; steps merged")
+    assert q(32, lgt.LGT_C128, 2) == ("tile_low13 | tile_high(q13,h10,rows8) | "
+                                      "tile_high(q23,h9,rows16) ; steps merged")
+    assert q(28, lgt.LGT_C128) == q(28, lgt.LGT_C128, 2)
 
 
 def test_plan_query_rejects_bad_arguments():
