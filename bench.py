@@ -150,6 +150,7 @@ def timed_workload(lgt, w, dtype, steps, warmup, stride):
         lgt.lgt_set_profiling(ctx, False)
         plan = lgt.lgt_plan_describe(ctx)
         state_bytes = info["state_bytes"]
+        ceiling = stream_ceiling(lgt, ctx)      # after the timed region
     finally:
         lgt.lgt_destroy(ctx)
     upd = steps * len(w.lambdas) * w.n_steps * (1 << n_links) * (n_links + 1)
@@ -158,6 +159,8 @@ def timed_workload(lgt, w, dtype, steps, warmup, stride):
     roof = roofline_from_stats(stats, state_bytes, None)
     if roof:
         roof["traffic"] = load_traffic(f"{name}:{'x'.join(map(str, w.L))}:{roof['kernel']}")
+        roof["stream_ceiling"] = ceiling
+        roof["frac_of_stream_ceiling"] = roof["achieved"] / ceiling["GBps"]
     return {"value": upd / elapsed, "elapsed": elapsed, "plan": plan,
             "us_per_trotter_step": elapsed / trotter_steps * 1e6,
             "algorithmic_hbm_frac_per_trotter_step":
@@ -231,6 +234,26 @@ def complex64_line(lgt, w, ref128, stride):
             "errors_per_result": errs}
 
 
+def stream_ceiling(lgt, ctx, reps=8):
+    """What the memory system gives a plain in-place pass over this state: R_z(0) on link 0
+    (`k_gate_rz`: every amplitude read, multiplied by exactly 1 and written back, no LDS, a
+    grid-stride loop over up to 16384 workgroups), every launch timed with HIP events.  The
+    state is left bit for bit as it was."""
+    sb = lgt.lgt_info(ctx)["state_bytes"]
+    lgt.lgt_apply_gate(ctx, lgt.LGT_GATE_RZ, 0, -1, 0.0)
+    lgt.lgt_sync(ctx)
+    lgt.lgt_set_profiling(ctx, 1)
+    for _ in range(reps):
+        lgt.lgt_apply_gate(ctx, lgt.LGT_GATE_RZ, 0, -1, 0.0)
+    lgt.lgt_sync(ctx)
+    n, ms = lgt.lgt_kernel_stats(ctx)["gate_rz"]
+    lgt.lgt_set_profiling(ctx, False)
+    avg = ms / n / 1e3
+    gbs = 2 * sb / avg / 1e9
+    return {"kernel": "k_gate_rz (R_z(0), in place)", "launches": int(n), "avg_us": avg * 1e6,
+            "GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+
+
 def hbm_rooflines(lgt, steps=6):
     """32 links (4x4): 32 GiB (complex64) and 64 GiB (complex128) states stream HBM on every
     pass.  Every pass kernel launch is timed with HIP events on its own dispatch; each family's
@@ -253,6 +276,7 @@ def hbm_rooflines(lgt, steps=6):
             stats = lgt.lgt_kernel_stats(ctx)
             lgt.lgt_set_profiling(ctx, False)
             plan = lgt.lgt_plan_describe(ctx)
+            ceiling = stream_ceiling(lgt, ctx, 4)
         finally:
             lgt.lgt_destroy(ctx)
         fam = {}
@@ -261,11 +285,12 @@ def hbm_rooflines(lgt, steps=6):
                 avg = ms / n / 1e3
                 fam[k] = {"launches": int(n), "avg_ms": avg * 1e3,
                           "achieved_GBps": 2 * sb / avg / 1e9,
-                          "frac": 2 * sb / avg / 1e9 / HBM_PEAK_GBS}
+                          "frac": 2 * sb / avg / 1e9 / HBM_PEAK_GBS,
+                          "frac_of_stream_ceiling": 2 * sb / avg / 1e9 / ceiling["GBps"]}
         out[f"4x4_{name}"] = {"state_bytes": sb, "plan": plan, "steps": steps,
                               "ms_per_trotter_step": el / steps * 1e3,
                               "algorithmic_frac_per_trotter_step": 2 * sb / (el / steps) / 1e9 / HBM_PEAK_GBS,
-                              "pass_families": fam}
+                              "pass_families": fam, "stream_ceiling": ceiling}
     return out
 
 
