@@ -144,9 +144,10 @@ def _oracle_readout(d, L, lam, n, order):
 
 
 def test_served_results_match_oracle():
-    """A served mix of 2x2 / 3x3 runs in complex64 and complex128 (and one 2x2x2 run),
-    submitted in three waves so that runs share rounds at different step offsets, each
-    spanning several rounds (25-step chunks, 100 steps a round for these small states)."""
+    """A served mix of 2x2 / 3x3 runs in complex64 and complex128 (and 2x2x2 runs in both:
+    the complex128 one on the register-bit high tile), submitted in three waves so that runs
+    share rounds at different step offsets, each spanning several rounds (25-step chunks,
+    100 steps a round for these small states)."""
     g = workloads.rng(stream=23)
     reqs = []
     for i in range(12):
@@ -154,6 +155,7 @@ def test_served_results_match_oracle():
         reqs.append((d, L, C128 if i % 2 else C64, float(g.uniform(0.1, 2.0)),
                      int(g.integers(60, 601)), TROT if i % 4 < 2 else SYM))
     reqs.append((3, (2, 2, 2), C64, 0.7, 6, SYM))
+    reqs.append((3, (2, 2, 2), C128, 1.3, 5, SYM))
     srv = lgt.lgt_server_create(8 << 30, 16, 25)
     try:
         tickets = []
