@@ -565,7 +565,7 @@ __global__ __launch_bounds__(64 << W) void k_tile(const DevInst *__restrict__ in
 // registers leave no room for a prefetch buffer: the next tile is loaded once the
 // current one is stored.
 // ---------------------------------------------------------------------------
-constexpr int kRbStaggerSleeps = 20;   // s_sleep 8 (512 clocks) each
+constexpr int kRbStaggerSleeps = 25;   // s_sleep 8 (512 clocks) each
 
 template <typename T, int W, int ROWB, bool TAN, bool TN, bool MERGE>
 __global__ __launch_bounds__(64 << W) void k_tile_rb(const DevInst *__restrict__ insts, int n,
